@@ -1,0 +1,158 @@
+/*
+ * mhd950.h -- C ABI of the MI355X (gfx950) Godunov step for compressible ideal MHD
+ * with constrained transport, and for isothermal gas coupled to N pressureless dust
+ * fluids by implicit drag.
+ *
+ * The operation behind these calls is the per-timestep finite-volume update of the
+ * paper (Aether.jl, Ho): the semi-discrete update of eq. (fv_update) with fluxes from
+ * reconstructed primitives and an approximate Riemann solver (Sec. "Reconstruction and
+ * Riemann Solvers"), the face-field update of eq. (ct) with upwind edge EMFs
+ * (Sec. "Constrained Transport"), the two-register stages of eq. (two_register) or the
+ * IMEX2P pair with closed-form drag solves (Secs. "Multifluid Dust", "Time
+ * Integration"), and the time step of eq. (cfl).  The interface mirrors the paper's
+ * Mesh / Simulation / set_initial_condition! / run! split (Sec. "User Interface"):
+ * a context is created once with every choice fixed and validated, the state is set,
+ * and steps are taken.
+ *
+ * Conventions
+ *   - Every call returns an mhd_status (0 = MHD_OK); no exception crosses the ABI.
+ *   - The grid is uniform, Cartesian and periodic in x, y and z.
+ *   - Memory: the caller owns the device workspace and the HIP stream; the library
+ *     borrows both for the lifetime of the context and allocates no device memory.
+ *     The context itself is a small host object freed by mhd_destroy.
+ *   - All work is enqueued on the caller's stream.  mhd_step is asynchronous;
+ *     mhd_dt_cfl, mhd_diagnostics and transfers to or from host memory synchronise it.
+ *   - Configuration is validated only in mhd_create (unsupported combinations are
+ *     rejected there, never during a step).
+ *   - Calls on one context are not thread safe; separate contexts are independent.
+ *
+ * Canonical state layout (FP64, what mhd_set_state/mhd_get_state exchange):
+ *   cell fields, each [nz][ny][nx] with x fastest, one after the other:
+ *     adiabatic MHD     : rho, M1, M2, M3, E                        (5 fields)
+ *     isothermal + dust : rho, M1, M2, M3, then for each species k
+ *                         rho_k, M_k1, M_k2, M_k3                    (4 + 4 N fields)
+ *   then, for MHD only, the face fields b1, b2, b3, each [nz][ny][nx]; b1[k][j][i] is
+ *   the area-averaged B_x on the face x_{i-1/2}, the left face of cell (i, j, k);
+ *   b2 and b3 likewise on y_{j-1/2} and z_{k-1/2}.
+ */
+#ifndef MHD950_H
+#define MHD950_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MHD_MAX_DUST 16
+
+typedef enum {
+    MHD_OK = 0,
+    MHD_E_INVAL = -1,       /* bad argument: null pointer, size, dt <= 0 or not finite */
+    MHD_E_UNSUPPORTED = -2, /* the scheme combination does not exist (mhd_create) */
+    MHD_E_NOMEM = -3,       /* workspace smaller than mhd_workspace_bytes, or host alloc failed */
+    MHD_E_DEVICE = -4,      /* a HIP runtime call failed */
+    MHD_E_NONFINITE = -5    /* the state holds NaN or Inf (found by the CFL reduction) */
+} mhd_status;
+
+typedef enum { MHD_EOS_ADIABATIC_MHD = 0, MHD_EOS_ISOTHERMAL_HYDRO = 1 } mhd_eos;
+typedef enum { MHD_RECON_DC = 0, MHD_RECON_PLM = 1, MHD_RECON_PPM = 2 } mhd_recon;
+typedef enum { MHD_RS_HLLE = 0, MHD_RS_HLLD = 1 } mhd_riemann;
+typedef enum {
+    MHD_INT_VL2 = 0,   /* donor-cell half step, then a full step with the chosen recon */
+    MHD_INT_RK2 = 1,   /* optimal two-stage SSP Runge-Kutta (paper's RK2) */
+    MHD_INT_IMEX2P = 2,/* ARS(2,2,2) pair, implicit weight 1 + 1/sqrt(2) (dust only) */
+    MHD_INT_EULER1 = 3 /* one forward-Euler stage; for tests */
+} mhd_integrator;
+typedef enum { MHD_PREC_FP64 = 0 } mhd_precision;
+
+/* Uniform periodic grid of nx*ny*nz cells covering a box of edges length[0..2]. */
+typedef struct {
+    int nx, ny, nz;
+    double length[3];
+} mhd_grid;
+
+/* Closure and physical parameters (Sec. "Newtonian Magnetohydrodynamics",
+ * Sec. "Multifluid Dust").  gamma: adiabatic index (MHD); cs_iso: isothermal sound
+ * speed (isothermal hydro); rho_floor, p_floor: floors applied to the primitives of
+ * the gas; dust_rho_floor: dust densities below it are read as the floor at rest;
+ * t_stop: constant stopping time of each of the ndust species; gas_accel: constant
+ * acceleration of the gas alone, applied as an unsplit source. */
+typedef struct {
+    int eos;
+    double gamma, cs_iso, rho_floor, p_floor;
+    int ndust;
+    double t_stop[MHD_MAX_DUST];
+    double dust_rho_floor;
+    double gas_accel[3];
+} mhd_physics;
+
+/* Scheme choices.  courant: the factor C of eq. (cfl) (the integrator's C_max is
+ * applied by the library); hlld_eps: degeneracy tolerance of HLLD relative to the
+ * fan's total pressure. */
+typedef struct {
+    int recon, riemann, integ;
+    double courant;
+    int prec;
+    double hlld_eps;
+} mhd_scheme;
+
+typedef struct mhd_ctx mhd_ctx;
+
+/* Bytes of device workspace a context of this configuration needs (256-byte aligned
+ * base expected).  Returns MHD_E_INVAL for null pointers or non-positive sizes and
+ * MHD_E_UNSUPPORTED for combinations mhd_create would reject. */
+mhd_status mhd_workspace_bytes(const mhd_grid* grid, const mhd_physics* phys,
+                               const mhd_scheme* scheme, size_t* bytes);
+
+/* Create a context on the current HIP device.  device_workspace: caller-owned device
+ * memory of at least mhd_workspace_bytes bytes, 256-byte aligned; hip_stream: the
+ * hipStream_t all work is enqueued on (NULL = the null stream).  Supported:
+ *   adiabatic MHD     with VL2, RK2 or EULER1, any recon, HLLE or HLLD, ndust = 0;
+ *   isothermal + dust with IMEX2P, DC or PLM recon, HLLE gas flux, 1 <= ndust <= 16.
+ * Anything else is MHD_E_UNSUPPORTED.  The state is undefined until mhd_set_state. */
+mhd_status mhd_create(const mhd_grid* grid, const mhd_physics* phys, const mhd_scheme* scheme,
+                      void* device_workspace, size_t bytes, void* hip_stream, mhd_ctx** out);
+
+/* Number of doubles in the canonical state of this context. */
+mhd_status mhd_state_len(const mhd_ctx* ctx, size_t* n);
+
+/* Copy a canonical FP64 state in (src on the device if src_is_device, else host
+ * memory; host copies complete before return).  Also computes the CFL step of the
+ * new state on the device. */
+mhd_status mhd_set_state(mhd_ctx* ctx, const double* src, int src_is_device);
+
+/* Copy the current state out in canonical layout; a copy to host memory completes
+ * before return, a copy to device memory is ordered on the stream. */
+mhd_status mhd_get_state(mhd_ctx* ctx, double* dst, int dst_is_device);
+
+/* Advance the state by exactly dt (one full step of the configured integrator; the
+ * Courant-limited step of the result is computed at its end).  Asynchronous.
+ * MHD_E_INVAL if dt <= 0 or not finite. */
+mhd_status mhd_step(mhd_ctx* ctx, double dt);
+
+/* The Courant-limited step C C_max min_cells min_d dx_d/(|v_d| + c_d) of the current
+ * state (eq. (cfl); c_d the directional fast speed for MHD, c_s for isothermal gas,
+ * 0 for dust; C_max = 1 for VL2/RK2/EULER1, 1/(1 + 1/sqrt 2) for IMEX2P).  Reads one
+ * double from the device (synchronises the stream).  MHD_E_NONFINITE if the state
+ * holds NaN or Inf. */
+mhd_status mhd_dt_cfl(mhd_ctx* ctx, double* dt);
+
+/* Volume integrals and extrema of the current state, in FP64 with a fixed-order
+ * (deterministic) reduction.  out must hold n >= 12 + ndust doubles:
+ *   out[0] gas mass, out[1..3] gas momentum, out[4] total energy (0 if isothermal),
+ *   out[5..7] volume integral of the face fields (0 without MHD), out[8] max |div B|
+ *   over cells, out[9 .. 8+ndust] dust masses, out[9+ndust .. 11+ndust] total momentum
+ *   of gas and dust.  Synchronises the stream. */
+mhd_status mhd_diagnostics(mhd_ctx* ctx, double* out, int n);
+
+/* Release the host context (the workspace stays the caller's). */
+void mhd_destroy(mhd_ctx* ctx);
+
+/* Static description of a status code. */
+const char* mhd_strerror(mhd_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

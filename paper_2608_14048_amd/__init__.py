@@ -1,0 +1,13 @@
+"""MI355X-native (gfx950) Godunov step for compressible CT-MHD and multifluid dust.
+
+The update of the paper's method (reconstruction of primitives, HLLE/HLLD face fluxes,
+Gardiner-Stone constrained-transport EMFs and face-field update, conserved update in
+the two-register stage form, IMEX2P with the closed-form implicit drag, CFL
+reduction) runs in hand-written HIP kernels behind the C ABI of include/mhd950.h;
+this package holds the ctypes binding (``binding``) and the seeded synthetic inputs
+(``inputs``).  Importing the package loads nothing; the library is opened on first
+use and its absence is an error.
+"""
+from .binding import (MhdError, Sim, load_library, make_grid, make_physics, make_scheme,  # noqa: F401
+                      mhd_create, mhd_destroy, mhd_diagnostics, mhd_dt_cfl, mhd_get_state,
+                      mhd_set_state, mhd_state_len, mhd_step, mhd_strerror, mhd_workspace_bytes)

@@ -1,0 +1,278 @@
+"""Thin ctypes binding of the C ABI in include/mhd950.h.
+
+The module-level functions carry the C names and only marshal arguments; every step
+of the update runs in the HIP kernels of libmhd950.so.  PyTorch provides the device
+workspace and the stream.  There is no fallback: if the library is missing or the
+device is unavailable, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmhd950.so")
+MAX_DUST = 16
+
+EOS = {"adiabatic_mhd": 0, "isothermal_hydro": 1}
+RECON = {"dc": 0, "plm": 1, "ppm": 2}
+RIEMANN = {"hlle": 0, "hlld": 1}
+INTEG = {"vl2": 0, "rk2": 1, "imex2p": 2, "euler1": 3}
+PREC = {"fp64": 0}
+
+STATUS = {0: "MHD_OK", -1: "MHD_E_INVAL", -2: "MHD_E_UNSUPPORTED", -3: "MHD_E_NOMEM",
+          -4: "MHD_E_DEVICE", -5: "MHD_E_NONFINITE"}
+
+
+class MhdError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {STATUS.get(code, code)} ({_strerror(code)})")
+
+
+class MhdGrid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("length", ctypes.c_double * 3)]
+
+
+class MhdPhysics(ctypes.Structure):
+    _fields_ = [("eos", ctypes.c_int), ("gamma", ctypes.c_double), ("cs_iso", ctypes.c_double),
+                ("rho_floor", ctypes.c_double), ("p_floor", ctypes.c_double),
+                ("ndust", ctypes.c_int), ("t_stop", ctypes.c_double * MAX_DUST),
+                ("dust_rho_floor", ctypes.c_double), ("gas_accel", ctypes.c_double * 3)]
+
+
+class MhdScheme(ctypes.Structure):
+    _fields_ = [("recon", ctypes.c_int), ("riemann", ctypes.c_int), ("integ", ctypes.c_int),
+                ("courant", ctypes.c_double), ("prec", ctypes.c_int), ("hlld_eps", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libmhd950.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing "
+                           "(run __graft_entry__.build() or python paper_2608_14048_amd/build.py)")
+    L = ctypes.CDLL(path)
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.mhd_workspace_bytes.argtypes = [ctypes.POINTER(MhdGrid), ctypes.POINTER(MhdPhysics),
+                                      ctypes.POINTER(MhdScheme), ctypes.POINTER(sz)]
+    L.mhd_create.argtypes = [ctypes.POINTER(MhdGrid), ctypes.POINTER(MhdPhysics),
+                             ctypes.POINTER(MhdScheme), vp, sz, vp, ctypes.POINTER(vp)]
+    L.mhd_state_len.argtypes = [vp, ctypes.POINTER(sz)]
+    L.mhd_set_state.argtypes = [vp, vp, ctypes.c_int]
+    L.mhd_get_state.argtypes = [vp, vp, ctypes.c_int]
+    L.mhd_step.argtypes = [vp, ctypes.c_double]
+    L.mhd_dt_cfl.argtypes = [vp, dp]
+    L.mhd_diagnostics.argtypes = [vp, dp, ctypes.c_int]
+    L.mhd_destroy.argtypes = [vp]
+    L.mhd_destroy.restype = None
+    L.mhd_strerror.argtypes = [ctypes.c_int]
+    L.mhd_strerror.restype = ctypes.c_char_p
+    for name in ("mhd_workspace_bytes", "mhd_create", "mhd_state_len", "mhd_set_state",
+                 "mhd_get_state", "mhd_step", "mhd_dt_cfl", "mhd_diagnostics"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _strerror(code: int) -> str:
+    try:
+        return load_library().mhd_strerror(code).decode()
+    except Exception:  # the library itself may be what is missing
+        return "?"
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise MhdError(code, where)
+
+
+# ---------------------------------------------------------------------------------
+# structures from Python values
+# ---------------------------------------------------------------------------------
+
+def make_grid(shape, length=(1.0, 1.0, 1.0)) -> MhdGrid:
+    g = MhdGrid()
+    g.nx, g.ny, g.nz = (int(s) for s in shape)
+    for a in range(3):
+        g.length[a] = float(length[a])
+    return g
+
+
+def make_physics(eos="adiabatic_mhd", gamma=5.0 / 3.0, cs=1.0, rho_floor=1e-12, p_floor=1e-10,
+                 tstop=(), dust_rho_floor=1e-12, gacc=(0.0, 0.0, 0.0)) -> MhdPhysics:
+    p = MhdPhysics()
+    p.eos = EOS[eos]
+    p.gamma, p.cs_iso, p.rho_floor, p.p_floor = gamma, cs, rho_floor, p_floor
+    p.ndust = len(tstop)
+    for k, t in enumerate(tstop):
+        p.t_stop[k] = float(t)
+    p.dust_rho_floor = dust_rho_floor
+    for a in range(3):
+        p.gas_accel[a] = float(gacc[a])
+    return p
+
+
+def make_scheme(recon="plm", riemann="hlld", integ="vl2", courant=0.3, prec="fp64",
+                hlld_eps=1e-12) -> MhdScheme:
+    s = MhdScheme()
+    s.recon, s.riemann, s.integ = RECON[recon], RIEMANN[riemann], INTEG[integ]
+    s.courant, s.prec, s.hlld_eps = courant, PREC[prec], hlld_eps
+    return s
+
+
+# ---------------------------------------------------------------------------------
+# the C calls under their own names
+# ---------------------------------------------------------------------------------
+
+def mhd_workspace_bytes(grid: MhdGrid, phys: MhdPhysics, scheme: MhdScheme) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load_library().mhd_workspace_bytes(ctypes.byref(grid), ctypes.byref(phys),
+                                              ctypes.byref(scheme), ctypes.byref(n)),
+           "mhd_workspace_bytes")
+    return n.value
+
+
+def mhd_create(grid, phys, scheme, workspace_ptr: int, nbytes: int, stream_ptr: int) -> int:
+    out = ctypes.c_void_p(0)
+    _check(load_library().mhd_create(ctypes.byref(grid), ctypes.byref(phys), ctypes.byref(scheme),
+                                     ctypes.c_void_p(workspace_ptr), ctypes.c_size_t(nbytes),
+                                     ctypes.c_void_p(stream_ptr), ctypes.byref(out)), "mhd_create")
+    return out.value
+
+
+def mhd_state_len(ctx: int) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load_library().mhd_state_len(ctypes.c_void_p(ctx), ctypes.byref(n)), "mhd_state_len")
+    return n.value
+
+
+def mhd_set_state(ctx: int, ptr: int, is_device: bool):
+    _check(load_library().mhd_set_state(ctypes.c_void_p(ctx), ctypes.c_void_p(ptr), int(is_device)),
+           "mhd_set_state")
+
+
+def mhd_get_state(ctx: int, ptr: int, is_device: bool):
+    _check(load_library().mhd_get_state(ctypes.c_void_p(ctx), ctypes.c_void_p(ptr), int(is_device)),
+           "mhd_get_state")
+
+
+def mhd_step(ctx: int, dt: float):
+    _check(load_library().mhd_step(ctypes.c_void_p(ctx), ctypes.c_double(dt)), "mhd_step")
+
+
+def mhd_dt_cfl(ctx: int) -> float:
+    out = ctypes.c_double(0.0)
+    _check(load_library().mhd_dt_cfl(ctypes.c_void_p(ctx), ctypes.byref(out)), "mhd_dt_cfl")
+    return out.value
+
+
+def mhd_diagnostics(ctx: int, n: int) -> np.ndarray:
+    out = np.zeros(n)
+    _check(load_library().mhd_diagnostics(ctypes.c_void_p(ctx),
+                                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n),
+           "mhd_diagnostics")
+    return out
+
+
+def mhd_destroy(ctx: int):
+    if ctx:
+        load_library().mhd_destroy(ctypes.c_void_p(ctx))
+
+
+def mhd_strerror(code: int) -> str:
+    return load_library().mhd_strerror(code).decode()
+
+
+# ---------------------------------------------------------------------------------
+# convenience object: Mesh + Simulation in one (cf. the paper's user interface)
+# ---------------------------------------------------------------------------------
+
+class Sim:
+    """A context on one device with its torch-owned workspace and stream.
+
+    Sim((nx, ny, nz), length, physics=dict(...), scheme=dict(...)) then set_state,
+    step / run, state, dt_cfl, diagnostics."""
+
+    def __init__(self, shape, length=(1.0, 1.0, 1.0), physics=None, scheme=None,
+                 device="cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the MI355X path has no CPU fallback")
+        load_library()
+        self.device = torch.device(device)
+        self.grid = make_grid(shape, length)
+        self.phys = make_physics(**(physics or {}))
+        self.scheme = make_scheme(**(scheme or {}))
+        self.shape = tuple(int(s) for s in shape)
+        self.nbytes = mhd_workspace_bytes(self.grid, self.phys, self.scheme)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = mhd_create(self.grid, self.phys, self.scheme, self.workspace.data_ptr(),
+                              self.nbytes, self.stream.cuda_stream)
+        self.n = mhd_state_len(self.ctx)
+        self.nq = 12 + self.phys.ndust
+
+    # state ------------------------------------------------------------------
+    def set_state(self, state):
+        import torch
+        if isinstance(state, torch.Tensor) and state.is_cuda:
+            t = state.detach().to(torch.float64).contiguous().reshape(-1)
+            assert t.numel() == self.n, (t.numel(), self.n)
+            mhd_set_state(self.ctx, t.data_ptr(), True)
+            self._keep = t  # the device copy is ordered on the stream
+        else:
+            a = np.ascontiguousarray(np.asarray(state, dtype=np.float64).reshape(-1))
+            assert a.size == self.n, (a.size, self.n)
+            mhd_set_state(self.ctx, a.ctypes.data, False)
+
+    def state(self, device: bool = False):
+        import torch
+        if device:
+            out = torch.empty(self.n, dtype=torch.float64, device=self.device)
+            mhd_get_state(self.ctx, out.data_ptr(), True)
+            return out
+        a = np.empty(self.n, dtype=np.float64)
+        mhd_get_state(self.ctx, a.ctypes.data, False)
+        return a
+
+    # stepping ---------------------------------------------------------------
+    def step(self, dt: float):
+        mhd_step(self.ctx, float(dt))
+
+    def dt_cfl(self) -> float:
+        return mhd_dt_cfl(self.ctx)
+
+    def run(self, nsteps: int, dts=None):
+        """Advance nsteps with the device CFL step (or a given dt sequence); returns the
+        list of dt taken."""
+        used = []
+        for k in range(nsteps):
+            dt = self.dt_cfl() if dts is None else float(dts[k])
+            self.step(dt)
+            used.append(dt)
+        return used
+
+    def diagnostics(self) -> np.ndarray:
+        return mhd_diagnostics(self.ctx, self.nq)
+
+    def close(self):
+        if getattr(self, "ctx", 0):
+            mhd_destroy(self.ctx)
+            self.ctx = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,316 @@
+// api.hip -- host runtime behind the C ABI of mhd950.h: validation at create time,
+// workspace carve-up, stage sequencing on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "../../include/mhd950.h"
+#include "launch.hpp"
+
+using namespace mhd;
+
+struct mhd_ctx {
+    mhd_grid grid;
+    mhd_physics phys;
+    mhd_scheme scheme;
+    Geo geo;
+    MhdParams mp;
+    DustParams dp;
+    hipStream_t stream;
+    bool is_mhd;
+    int nvar;       // fields of the canonical state
+    long long n;    // cells
+    // workspace views
+    double* reg[2]; // state registers (canonical layout each)
+    double* W;      // primitives
+    double* F;      // face fluxes, 3 direction blocks
+    double* E;      // edge EMFs (MHD)
+    double* partial;
+    double* scalars;  // [0] dt of the current state, [1..] diagnostics
+    int cur;        // register holding the current state
+    double cfl_scale;
+};
+
+namespace {
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t reg, W, F, E, partial, scalars, total;
+};
+
+int state_fields(const mhd_physics* p)
+{
+    return p->eos == MHD_EOS_ADIABATIC_MHD ? 8 : 4 * (1 + p->ndust);
+}
+
+mhd_status validate(const mhd_grid* g, const mhd_physics* p, const mhd_scheme* s)
+{
+    if (!g || !p || !s) return MHD_E_INVAL;
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1) return MHD_E_INVAL;
+    for (int a = 0; a < 3; ++a)
+        if (!(g->length[a] > 0.0) || !std::isfinite(g->length[a])) return MHD_E_INVAL;
+    if ((long long)g->nx * g->ny * g->nz > (1LL << 34)) return MHD_E_INVAL;
+    if (!(s->courant > 0.0) || !std::isfinite(s->courant)) return MHD_E_INVAL;
+    if (s->prec != MHD_PREC_FP64) return MHD_E_UNSUPPORTED;
+    if (s->recon < MHD_RECON_DC || s->recon > MHD_RECON_PPM) return MHD_E_UNSUPPORTED;
+    if (s->riemann != MHD_RS_HLLE && s->riemann != MHD_RS_HLLD) return MHD_E_UNSUPPORTED;
+    if (p->eos == MHD_EOS_ADIABATIC_MHD) {
+        if (p->ndust != 0) return MHD_E_UNSUPPORTED;
+        if (s->integ != MHD_INT_VL2 && s->integ != MHD_INT_RK2 && s->integ != MHD_INT_EULER1)
+            return MHD_E_UNSUPPORTED;
+        if (!(p->gamma > 1.0)) return MHD_E_INVAL;
+    } else if (p->eos == MHD_EOS_ISOTHERMAL_HYDRO) {
+        if (p->ndust < 1 || p->ndust > MHD_MAX_DUST) return MHD_E_UNSUPPORTED;
+        if (s->integ != MHD_INT_IMEX2P) return MHD_E_UNSUPPORTED;
+        if (s->riemann != MHD_RS_HLLE) return MHD_E_UNSUPPORTED;  // no isothermal HLLD here
+        if (s->recon == MHD_RECON_PPM) return MHD_E_UNSUPPORTED;
+        if (!(p->cs_iso > 0.0)) return MHD_E_INVAL;
+        for (int k = 0; k < p->ndust; ++k)
+            if (!(p->t_stop[k] > 0.0) || !std::isfinite(p->t_stop[k])) return MHD_E_INVAL;
+    } else {
+        return MHD_E_UNSUPPORTED;
+    }
+    return MHD_OK;
+}
+
+Layout layout(const mhd_grid* g, const mhd_physics* p)
+{
+    const long long n = (long long)g->nx * g->ny * g->nz;
+    const size_t field = (size_t)n * sizeof(double);
+    const int nv = state_fields(p);
+    const bool is_mhd = p->eos == MHD_EOS_ADIABATIC_MHD;
+    Layout L;
+    L.reg = align256(field * nv);
+    L.W = align256(field * nv);
+    L.F = align256(field * (is_mhd ? 21 : 3 * nv));
+    L.E = is_mhd ? align256(field * 3) : 0;
+    const size_t nb = blocks_for(n);
+    L.partial = align256(nb * sizeof(double) * (size_t)diag_count(MHD_MAX_DUST));
+    L.scalars = align256(sizeof(double) * 64);
+    L.total = 2 * L.reg + L.W + L.F + L.E + L.partial + L.scalars;
+    return L;
+}
+
+mhd_status dev(hipError_t e) { return e == hipSuccess ? MHD_OK : MHD_E_DEVICE; }
+
+// Compute the CFL step of the current state into scalars[0].
+mhd_status refresh_cfl(mhd_ctx* c)
+{
+    const double* U = c->reg[c->cur];
+    if (c->is_mhd) return dev(launch_cfl_mhd(c->geo, c->mp, U, c->partial, c->scalars, c->cfl_scale, c->stream));
+    return dev(launch_cfl_dust(c->geo, c->dp, U, c->partial, c->scalars, c->cfl_scale, c->stream));
+}
+
+mhd_status mhd_stage(mhd_ctx* c, int recon, const double* in, const double* base, double* out,
+                     StageCoef co)
+{
+    hipError_t e = launch_mhd_prims(c->geo, c->mp, in, c->W, c->stream);
+    if (e == hipSuccess) e = launch_mhd_fluxes(c->geo, c->mp, recon, c->scheme.riemann, c->W, in, c->F, c->stream);
+    if (e == hipSuccess) e = launch_mhd_edges(c->geo, c->W, c->F, c->E, c->stream);
+    if (e == hipSuccess) e = launch_mhd_update(c->geo, c->mp, in, base, c->F, c->E, out, co, c->stream);
+    return dev(e);
+}
+
+mhd_status step_mhd(mhd_ctx* c, double dt)
+{
+    double* A = c->reg[c->cur];
+    double* B = c->reg[1 - c->cur];
+    mhd_status st;
+    switch (c->scheme.integ) {
+    case MHD_INT_VL2:
+        // predictor: donor cell, half step; corrector: configured recon, full step from U*
+        st = mhd_stage(c, MHD_RECON_DC, A, A, B, StageCoef{0.0, 1.0, 0.5 * dt});
+        if (st != MHD_OK) return st;
+        st = mhd_stage(c, c->scheme.recon, B, A, A, StageCoef{0.0, 1.0, dt});
+        break;
+    case MHD_INT_RK2:
+        st = mhd_stage(c, c->scheme.recon, A, A, B, StageCoef{0.0, 1.0, dt});
+        if (st != MHD_OK) return st;
+        st = mhd_stage(c, c->scheme.recon, B, A, A, StageCoef{0.5, 0.5, 0.5 * dt});
+        break;
+    default:  // EULER1
+        st = mhd_stage(c, c->scheme.recon, A, A, B, StageCoef{0.0, 1.0, dt});
+        c->cur = 1 - c->cur;
+        break;
+    }
+    return st;
+}
+
+mhd_status step_dust(mhd_ctx* c, double dt)
+{
+    double* u = c->reg[c->cur];
+    double* U1 = c->reg[1 - c->cur];
+    const int recon = c->scheme.recon;
+    hipError_t e = launch_dust_prims(c->geo, c->dp, u, c->W, c->stream);
+    if (e == hipSuccess) e = launch_dust_fluxes(c->geo, c->dp, recon, c->W, c->F, c->stream);
+    if (e == hipSuccess) e = launch_imex_stage1(c->geo, c->dp, u, c->F, U1, dt, c->stream);
+    if (e == hipSuccess) e = launch_dust_prims(c->geo, c->dp, U1, c->W, c->stream);
+    if (e == hipSuccess) e = launch_dust_fluxes(c->geo, c->dp, recon, c->W, c->F, c->stream);
+    if (e == hipSuccess) e = launch_imex_stage2(c->geo, c->dp, u, U1, c->F, dt, c->stream);
+    return dev(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mhd_strerror(mhd_status s)
+{
+    switch (s) {
+    case MHD_OK: return "ok";
+    case MHD_E_INVAL: return "invalid argument";
+    case MHD_E_UNSUPPORTED: return "unsupported scheme combination";
+    case MHD_E_NOMEM: return "workspace too small or host allocation failed";
+    case MHD_E_DEVICE: return "HIP runtime error";
+    case MHD_E_NONFINITE: return "state holds NaN or Inf";
+    }
+    return "unknown status";
+}
+
+mhd_status mhd_workspace_bytes(const mhd_grid* grid, const mhd_physics* phys,
+                               const mhd_scheme* scheme, size_t* bytes)
+{
+    if (!bytes) return MHD_E_INVAL;
+    mhd_status st = validate(grid, phys, scheme);
+    if (st != MHD_OK) return st;
+    *bytes = layout(grid, phys).total;
+    return MHD_OK;
+}
+
+mhd_status mhd_create(const mhd_grid* grid, const mhd_physics* phys, const mhd_scheme* scheme,
+                      void* device_workspace, size_t bytes, void* hip_stream, mhd_ctx** out)
+{
+    if (!out) return MHD_E_INVAL;
+    *out = nullptr;
+    mhd_status st = validate(grid, phys, scheme);
+    if (st != MHD_OK) return st;
+    if (!device_workspace || ((uintptr_t)device_workspace & 255u)) return MHD_E_INVAL;
+    const Layout L = layout(grid, phys);
+    if (bytes < L.total) return MHD_E_NOMEM;
+
+    mhd_ctx* c = new (std::nothrow) mhd_ctx;
+    if (!c) return MHD_E_NOMEM;
+    std::memset(c, 0, sizeof(*c));
+    c->grid = *grid;
+    c->phys = *phys;
+    c->scheme = *scheme;
+    c->stream = (hipStream_t)hip_stream;
+    c->is_mhd = phys->eos == MHD_EOS_ADIABATIC_MHD;
+    c->nvar = state_fields(phys);
+    c->n = (long long)grid->nx * grid->ny * grid->nz;
+
+    Geo& g = c->geo;
+    g.nx = grid->nx; g.ny = grid->ny; g.nz = grid->nz;
+    g.n = c->n;
+    const int ns[3] = {grid->nx, grid->ny, grid->nz};
+    for (int a = 0; a < 3; ++a) {
+        g.dx[a] = grid->length[a] / ns[a];
+        g.inv_dx[a] = 1.0 / g.dx[a];
+    }
+    c->mp.gamma = phys->gamma;
+    c->mp.gm1inv = 1.0 / (phys->gamma - 1.0);
+    c->mp.rho_floor = phys->rho_floor;
+    c->mp.p_floor = phys->p_floor;
+    c->mp.hlld_eps = scheme->hlld_eps;
+    c->dp.nd = phys->ndust;
+    c->dp.cs = phys->cs_iso;
+    c->dp.rho_floor = phys->rho_floor;
+    c->dp.dust_floor = phys->dust_rho_floor;
+    for (int a = 0; a < 3; ++a) {
+        c->mp.gacc[a] = phys->gas_accel[a];
+        c->dp.gacc[a] = phys->gas_accel[a];
+    }
+    for (int k = 0; k < phys->ndust; ++k) c->dp.ts[k] = phys->t_stop[k];
+    const double cmax = scheme->integ == MHD_INT_IMEX2P ? 1.0 / (1.0 + 1.0 / std::sqrt(2.0)) : 1.0;
+    c->cfl_scale = scheme->courant * cmax;
+
+    char* base = (char*)device_workspace;
+    c->reg[0] = (double*)base; base += L.reg;
+    c->reg[1] = (double*)base; base += L.reg;
+    c->W = (double*)base; base += L.W;
+    c->F = (double*)base; base += L.F;
+    c->E = L.E ? (double*)base : nullptr; base += L.E;
+    c->partial = (double*)base; base += L.partial;
+    c->scalars = (double*)base;
+    c->cur = 0;
+    *out = c;
+    return MHD_OK;
+}
+
+mhd_status mhd_state_len(const mhd_ctx* c, size_t* n)
+{
+    if (!c || !n) return MHD_E_INVAL;
+    *n = (size_t)c->n * c->nvar;
+    return MHD_OK;
+}
+
+mhd_status mhd_set_state(mhd_ctx* c, const double* src, int src_is_device)
+{
+    if (!c || !src) return MHD_E_INVAL;
+    const size_t bytes = (size_t)c->n * c->nvar * sizeof(double);
+    hipError_t e = hipMemcpyAsync(c->reg[c->cur], src, bytes,
+                                  src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                  c->stream);
+    if (e != hipSuccess) return MHD_E_DEVICE;
+    if (!src_is_device) {
+        e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return MHD_E_DEVICE;
+    }
+    return refresh_cfl(c);
+}
+
+mhd_status mhd_get_state(mhd_ctx* c, double* dst, int dst_is_device)
+{
+    if (!c || !dst) return MHD_E_INVAL;
+    const size_t bytes = (size_t)c->n * c->nvar * sizeof(double);
+    hipError_t e = hipMemcpyAsync(dst, c->reg[c->cur], bytes,
+                                  dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                  c->stream);
+    if (e != hipSuccess) return MHD_E_DEVICE;
+    if (!dst_is_device) return dev(hipStreamSynchronize(c->stream));
+    return MHD_OK;
+}
+
+mhd_status mhd_step(mhd_ctx* c, double dt)
+{
+    if (!c) return MHD_E_INVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return MHD_E_INVAL;
+    mhd_status st = c->is_mhd ? step_mhd(c, dt) : step_dust(c, dt);
+    if (st != MHD_OK) return st;
+    return refresh_cfl(c);
+}
+
+mhd_status mhd_dt_cfl(mhd_ctx* c, double* dt)
+{
+    if (!c || !dt) return MHD_E_INVAL;
+    double h = 0.0;
+    hipError_t e = hipMemcpyAsync(&h, c->scalars, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return MHD_E_DEVICE;
+    *dt = h;
+    if (!std::isfinite(h) || !(h > 0.0)) return MHD_E_NONFINITE;
+    return MHD_OK;
+}
+
+mhd_status mhd_diagnostics(mhd_ctx* c, double* out, int n)
+{
+    if (!c || !out) return MHD_E_INVAL;
+    const int nq = diag_count(c->phys.ndust);
+    if (n < nq) return MHD_E_INVAL;
+    hipError_t e = launch_diag(c->geo, c->is_mhd ? 1 : 0, c->is_mhd ? 0 : c->phys.ndust,
+                               c->reg[c->cur], c->partial, c->scalars + 1, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, c->scalars + 1, sizeof(double) * nq, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return MHD_E_DEVICE;
+    // keep the CFL scalar of the state (the diagnostics reuse only the partial buffer)
+    return MHD_OK;
+}
+
+void mhd_destroy(mhd_ctx* c) { delete c; }
+
+}  // extern "C"

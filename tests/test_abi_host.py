@@ -1,0 +1,92 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports every
+function the header declares, and rejects bad configurations before any launch."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2608_14048_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mhd950.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(B.LIB_PATH),
+                                reason="libmhd950.so not built (run __graft_entry__.build())")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mhd_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(B.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def _ws(shape=(8, 8, 8), **kw):
+    phys = {k: kw.pop(k) for k in list(kw) if k in ("eos", "tstop", "cs", "gamma", "gacc")}
+    return B.make_grid(shape), B.make_physics(**phys), B.make_scheme(**kw)
+
+
+def test_workspace_and_validation():
+    g, p, s = _ws()
+    nb = B.mhd_workspace_bytes(g, p, s)
+    assert nb >= 2 * 8 * 512 * 8  # two FP64 registers of 8 fields at least
+    # bigger grid, bigger workspace
+    g2, p2, s2 = _ws((16, 8, 8))
+    assert B.mhd_workspace_bytes(g2, p2, s2) > nb
+    bad = [
+        dict(shape=(0, 8, 8)),
+        dict(courant=0.0),
+        dict(courant=float("nan")),
+    ]
+    for kw in bad:
+        with pytest.raises(B.MhdError) as e:
+            B.mhd_workspace_bytes(*_ws(**kw))
+        assert e.value.code == -1
+    unsupported = [
+        dict(integ="imex2p"),                                    # IMEX2P without dust
+        dict(eos="isothermal_hydro", tstop=(1.0,), integ="vl2"),  # dust needs IMEX2P
+        dict(eos="isothermal_hydro", tstop=(1.0,), integ="imex2p", riemann="hlld"),
+        dict(eos="isothermal_hydro", tstop=(1.0,), integ="imex2p", riemann="hlle", recon="ppm"),
+        dict(eos="isothermal_hydro", tstop=(), integ="imex2p", riemann="hlle"),
+        dict(eos="isothermal_hydro", tstop=(1.0,) * 17, integ="imex2p", riemann="hlle"),
+    ]
+    for kw in unsupported:
+        shape = kw.pop("shape", (8, 8, 8))
+        if len(kw.get("tstop", ())) > 16:
+            # more species than the ABI holds is refused by the Python marshaller first
+            with pytest.raises(IndexError):
+                _ws(shape, **kw)
+            continue
+        with pytest.raises(B.MhdError) as e:
+            B.mhd_workspace_bytes(*_ws(shape, **kw))
+        assert e.value.code == -2, kw
+
+
+def test_create_checks_workspace_before_touching_the_device():
+    g, p, s = _ws()
+    nb = B.mhd_workspace_bytes(g, p, s)
+    fake = 1 << 40  # never dereferenced: create only carves pointers
+    with pytest.raises(B.MhdError) as e:
+        B.mhd_create(g, p, s, fake, nb - 256, 0)
+    assert e.value.code == -3
+    with pytest.raises(B.MhdError) as e:
+        B.mhd_create(g, p, s, fake + 8, nb, 0)  # misaligned
+    assert e.value.code == -1
+    ctx = B.mhd_create(g, p, s, fake, nb, 0)
+    try:
+        assert B.mhd_state_len(ctx) == 8 * 512
+        for bad_dt in (0.0, -1.0, float("nan"), float("inf")):
+            with pytest.raises(B.MhdError) as e:
+                B.mhd_step(ctx, bad_dt)
+            assert e.value.code == -1
+    finally:
+        B.mhd_destroy(ctx)
+    assert B.mhd_strerror(-5) == "state holds NaN or Inf"

@@ -1,0 +1,365 @@
+"""GPU (HIP, through the C ABI) against the CPU oracle, element by element.
+
+Tolerance (the method's FP64 contract): every conserved class agrees to 1e-12 of its
+scale after one step from the same input, and to 1e-10 after many steps driven by the
+oracle's own dt sequence.  The scale of a class is the largest magnitude the class
+takes in the oracle's state (momentum: max rho(|v| + c_s)), so near-zero fields are
+not divided by themselves.  The GPU contracts a*b+c into FMAs and multiplies by
+reciprocals where the oracle divides; both round differently at the last bit only.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2608_14048_amd import binding as B
+from paper_2608_14048_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+STEP_TOL = 1e-12
+RUN_TOL = 1e-10
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# ----------------------------------------------------------------------------------
+# problem set-up shared by both sides
+# ----------------------------------------------------------------------------------
+
+class Pair:
+    """The same configuration on the oracle and on the GPU."""
+
+    def __init__(self, shape, length=(1.0, 1.0, 1.0), eos="adiabatic_mhd", gamma=5.0 / 3.0,
+                 tstop=(), gacc=(0.0, 0.0, 0.0), recon="plm", riemann="hlld", integ="vl2",
+                 courant=0.3):
+        self.shape, self.eos, self.gamma, self.nd = tuple(shape), eos, gamma, len(tstop)
+        self.cfg = oracle.make_cfg(shape, length=length, eos=eos, gamma=gamma, tstop=tstop,
+                                   gacc=gacc, recon=recon, riemann=riemann, integ=integ,
+                                   courant=courant)
+        self.sim = B.Sim(shape, length, physics=dict(eos=eos, gamma=gamma, tstop=tuple(tstop),
+                                                     gacc=gacc),
+                         scheme=dict(recon=recon, riemann=riemann, integ=integ, courant=courant))
+
+    def close(self):
+        self.sim.close()
+
+
+def class_errors(pair, got, ref):
+    """max |got - ref| / scale per conserved class."""
+    n = int(np.prod(pair.shape))
+    g = got.reshape(-1, n)
+    r = ref.reshape(-1, n)
+    out = {}
+    if pair.eos == "adiabatic_mhd":
+        rho = r[0]
+        bcc2 = r[5] ** 2 + r[6] ** 2 + r[7] ** 2
+        ke = 0.5 * (r[1] ** 2 + r[2] ** 2 + r[3] ** 2) / rho
+        p = np.maximum((pair.gamma - 1) * (r[4] - ke - 0.5 * bcc2), 1e-10)
+        speed = np.sqrt(r[1] ** 2 + r[2] ** 2 + r[3] ** 2) / rho + np.sqrt(pair.gamma * p / rho)
+        scales = {"rho": np.abs(rho).max(), "M": (rho * speed).max(), "E": np.abs(r[4]).max(),
+                  "B": np.abs(r[5:8]).max()}
+        rows = {"rho": [0], "M": [1, 2, 3], "E": [4], "B": [5, 6, 7]}
+    else:
+        scales, rows = {}, {}
+        for s in range(pair.nd + 1):
+            rho = r[4 * s]
+            speed = np.sqrt(r[4 * s + 1] ** 2 + r[4 * s + 2] ** 2 + r[4 * s + 3] ** 2) / rho + 1.0
+            scales[f"rho{s}"] = np.abs(rho).max()
+            scales[f"M{s}"] = (rho * speed).max()
+            rows[f"rho{s}"] = [4 * s]
+            rows[f"M{s}"] = [4 * s + 1, 4 * s + 2, 4 * s + 3]
+    for k, rr in rows.items():
+        out[k] = float(np.abs(g[rr] - r[rr]).max() / scales[k])
+    return out
+
+
+def assert_close(pair, got, ref, tol, what):
+    e = class_errors(pair, got, ref)
+    worst = max(e.values())
+    _say(f"  {what}: worst class error {worst:.3e}  {e}")
+    assert np.all(np.isfinite(got))
+    assert worst <= tol, (what, e)
+
+
+def random_mhd(shape, seed, length=(1.0, 1.0, 1.0), amp=0.5):
+    """Rough random MHD state (independent cell values), B from a random potential."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    full = (nz, ny, nx)
+    rho = rng.uniform(0.5, 1.5, full)
+    v = [rng.normal(0, amp, full) for _ in range(3)]
+    p = rng.uniform(0.4, 1.2, full)
+    pots = [rng.normal(0, 0.3 / max(shape), full) for _ in range(3)]
+    dx = [length[a] / shape[a] for a in range(3)]
+    b1, b2, b3 = I.faces_from_potential(*pots, *dx)
+    return I.mhd_state(rho, v[0], v[1], v[2], p * 1.5, b1 + 0.6, b2 - 0.3, b3 + 0.2)
+
+
+def dust_problem(shape, seed=0, nd=8, noise=1e-2):
+    st, ts = I.dust_drift(shape=shape, nd=nd, seed=seed, noise=noise)
+    return st, ts
+
+
+# ----------------------------------------------------------------------------------
+# time step
+# ----------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["wave32", "turb", "ragged", "dust"])
+def test_dt_cfl_parity(case):
+    if case == "wave32":
+        st, _ = I.linear_wave(32)
+        pr = Pair((32, 32, 32))
+    elif case == "turb":
+        st = I.turbulence(32, seed=3)
+        pr = Pair((32, 32, 32), recon="ppm")
+    elif case == "ragged":
+        st = random_mhd((19, 13, 7), 5, length=(1.9, 1.3, 0.7))
+        pr = Pair((19, 13, 7), length=(1.9, 1.3, 0.7))
+    else:
+        st, ts = dust_problem((12, 10, 8), nd=8)
+        pr = Pair((12, 10, 8), eos="isothermal_hydro", tstop=ts, gacc=(0.05, 0, 0),
+                  riemann="hlle", integ="imex2p")
+    try:
+        pr.sim.set_state(st)
+        g = pr.sim.dt_cfl()
+        o = oracle.dt_cfl(pr.cfg, st)
+        _say(f"  {case}: dt gpu {g!r} oracle {o!r}")
+        assert abs(g - o) <= 1e-14 * o
+    finally:
+        pr.close()
+
+
+# ----------------------------------------------------------------------------------
+# one step from the same input
+# ----------------------------------------------------------------------------------
+
+MHD_CASES = [
+    # name, shape, length, recon, riemann, integ, state maker
+    ("wave32-plm-hlld-vl2", (32, 32, 32), (1, 1, 1), "plm", "hlld", "vl2", lambda: I.linear_wave(32)[0]),
+    ("turb32-ppm-hlld-vl2", (32, 32, 32), (1, 1, 1), "ppm", "hlld", "vl2", lambda: I.turbulence(32, seed=1)),
+    ("ragged-ppm-hlld-vl2", (37, 21, 11), (1.85, 1.05, 0.55), "ppm", "hlld", "vl2",
+     lambda: random_mhd((37, 21, 11), 2, (1.85, 1.05, 0.55))),
+    ("ragged-plm-hlle-rk2", (23, 17, 9), (1, 1, 1), "plm", "hlle", "rk2",
+     lambda: random_mhd((23, 17, 9), 3)),
+    ("ragged-dc-hlld-euler1", (16, 9, 5), (1, 1, 1), "dc", "hlld", "euler1",
+     lambda: random_mhd((16, 9, 5), 4)),
+    ("ragged-ppm-hlle-vl2", (20, 12, 12), (1, 0.6, 0.6), "ppm", "hlle", "vl2",
+     lambda: random_mhd((20, 12, 12), 6, (1, 0.6, 0.6))),
+    ("thin-plm-hlld-vl2", (24, 1, 3), (1, 1 / 24, 3 / 24), "plm", "hlld", "vl2",
+     lambda: random_mhd((24, 1, 3), 7, (1, 1 / 24, 3 / 24))),
+]
+
+
+@pytest.mark.parametrize("case", MHD_CASES, ids=[c[0] for c in MHD_CASES])
+def test_one_step_parity_mhd(case):
+    name, shape, length, recon, riemann, integ, make = case
+    st = make()
+    pr = Pair(shape, length=length, recon=recon, riemann=riemann, integ=integ)
+    try:
+        dt = oracle.dt_cfl(pr.cfg, st)
+        ref = oracle.step(pr.cfg, st, dt)
+        pr.sim.set_state(st)
+        pr.sim.step(dt)
+        assert_close(pr, pr.sim.state(), ref, STEP_TOL, name)
+    finally:
+        pr.close()
+
+
+@pytest.mark.parametrize("recon,nd,shape", [("plm", 8, (24, 20, 18)), ("dc", 3, (13, 11, 7)),
+                                             ("plm", 1, (16, 16, 1))])
+def test_one_step_parity_dust(recon, nd, shape):
+    st, ts = dust_problem(shape, seed=1, nd=nd)
+    pr = Pair(shape, eos="isothermal_hydro", tstop=ts, gacc=(0.05, 0.0, 0.0), recon=recon,
+              riemann="hlle", integ="imex2p")
+    try:
+        dt = oracle.dt_cfl(pr.cfg, st)
+        ref = oracle.step(pr.cfg, st, dt)
+        pr.sim.set_state(st)
+        pr.sim.step(dt)
+        assert_close(pr, pr.sim.state(), ref, STEP_TOL, f"dust {recon} nd={nd}")
+    finally:
+        pr.close()
+    # strongly stiff drag: stopping times 1e3 x shorter, the same Courant-limited step
+    # (dt / t_s up to ~1e4); the explicit part stays within its stability limit
+    ts_stiff = ts * 1e-3
+    pr = Pair(shape, eos="isothermal_hydro", tstop=ts_stiff, gacc=(0.05, 0.0, 0.0), recon=recon,
+              riemann="hlle", integ="imex2p")
+    try:
+        dt = oracle.dt_cfl(pr.cfg, st)
+        _say(f"  stiff: dt/min(t_s) = {dt / ts_stiff.min():.3g}")
+        ref = oracle.step(pr.cfg, st, dt)
+        pr.sim.set_state(st)
+        pr.sim.step(dt)
+        assert_close(pr, pr.sim.state(), ref, STEP_TOL, f"dust {recon} nd={nd} stiff")
+    finally:
+        pr.close()
+
+
+# ----------------------------------------------------------------------------------
+# many steps, the oracle's dt sequence
+# ----------------------------------------------------------------------------------
+
+def run_both(pr, st, nsteps, check_dt=True):
+    s = st.copy()
+    pr.sim.set_state(st)
+    for k in range(nsteps):
+        dt = oracle.dt_cfl(pr.cfg, s)
+        if check_dt:
+            g = pr.sim.dt_cfl()
+            assert abs(g - dt) <= 1e-12 * dt, (k, g, dt)
+        s = oracle.step(pr.cfg, s, dt)
+        pr.sim.step(dt)
+    return s, pr.sim.state()
+
+
+def test_linear_wave_32_twenty_steps():
+    """The small MHD workload as configured: fast wave along the diagonal, 32^3,
+    VL2 + PLM + HLLD + CT, CFL 0.3, 20 steps."""
+    st, _ = I.linear_wave(32)
+    pr = Pair((32, 32, 32), recon="plm", riemann="hlld", integ="vl2")
+    try:
+        ref, got = run_both(pr, st, 20)
+        assert_close(pr, got, ref, RUN_TOL, "wave32 x20")
+        # relative to the 1e-6 perturbation itself, not only to the background
+        dpert = np.abs(got - ref).max() / np.abs(ref - I.linear_wave(32, t=0.0)[0]).max()
+        _say(f"  error relative to the perturbation {dpert:.3e}")
+        assert dpert < 1e-7
+    finally:
+        pr.close()
+
+
+def test_turbulence_64_hundred_steps():
+    """Decaying turbulence recipe at 64^3, VL2 + PPM + HLLD + CT, 100 steps."""
+    st = I.turbulence(64, seed=1)
+    pr = Pair((64, 64, 64), recon="ppm", riemann="hlld", integ="vl2")
+    try:
+        ref, got = run_both(pr, st, 100)
+        assert_close(pr, got, ref, RUN_TOL, "turb64 x100")
+    finally:
+        pr.close()
+
+
+def test_dust_48_fifty_steps():
+    """Gas + 8 dust species recipe at 48^3, IMEX2P + PLM, 50 steps."""
+    st, ts = dust_problem((48, 48, 48), seed=0, nd=8, noise=1e-3)
+    pr = Pair((48, 48, 48), eos="isothermal_hydro", tstop=ts, gacc=(0.05, 0, 0), recon="plm",
+              riemann="hlle", integ="imex2p")
+    try:
+        ref, got = run_both(pr, st, 50)
+        assert_close(pr, got, ref, RUN_TOL, "dust48 x50")
+    finally:
+        pr.close()
+
+
+# ----------------------------------------------------------------------------------
+# full sizes of the benchmarked workloads (one step, every element)
+# ----------------------------------------------------------------------------------
+
+def test_turbulence_256_one_step_full_size():
+    st = I.turbulence(256, seed=0)
+    pr = Pair((256, 256, 256), recon="ppm", riemann="hlld", integ="vl2")
+    try:
+        dt = oracle.dt_cfl(pr.cfg, st)
+        pr.sim.set_state(st)
+        assert abs(pr.sim.dt_cfl() - dt) <= 1e-14 * dt
+        pr.sim.step(dt)
+        got = pr.sim.state()
+        ref = oracle.step(pr.cfg, st, dt)
+        assert_close(pr, got, ref, STEP_TOL, "turb256 x1")
+    finally:
+        pr.close()
+
+
+def test_dust_192_one_step_full_size():
+    st, ts = dust_problem((192, 192, 192), seed=0, nd=8, noise=1e-3)
+    pr = Pair((192, 192, 192), eos="isothermal_hydro", tstop=ts, gacc=(0.05, 0, 0), recon="plm",
+              riemann="hlle", integ="imex2p")
+    try:
+        dt = oracle.dt_cfl(pr.cfg, st)
+        pr.sim.set_state(st)
+        pr.sim.step(dt)
+        got = pr.sim.state()
+        ref = oracle.step(pr.cfg, st, dt)
+        assert_close(pr, got, ref, STEP_TOL, "dust192 x1")
+    finally:
+        pr.close()
+
+
+# ----------------------------------------------------------------------------------
+# invariants of the GPU path
+# ----------------------------------------------------------------------------------
+
+def test_bitwise_rerun_and_restart():
+    st = I.turbulence(32, seed=2)
+    a = Pair((32, 32, 32), recon="ppm")
+    b = Pair((32, 32, 32), recon="ppm")
+    try:
+        a.sim.set_state(st)
+        da = a.sim.run(10)
+        sa = a.sim.state()
+        b.sim.set_state(st)
+        db = b.sim.run(5)
+        mid = b.sim.state()
+        b.close()
+        c = Pair((32, 32, 32), recon="ppm")
+        c.sim.set_state(mid)
+        db += c.sim.run(5)
+        sc = c.sim.state()
+        c.close()
+        assert da == db
+        assert np.array_equal(sa, sc)
+    finally:
+        a.close()
+
+
+def test_state_round_trip_and_device_copy():
+    import torch
+    st = random_mhd((16, 12, 8), 9)
+    pr = Pair((16, 12, 8))
+    try:
+        pr.sim.set_state(st)
+        assert np.array_equal(pr.sim.state(), st)
+        dev = torch.from_numpy(st).to("cuda:0")
+        pr.sim.set_state(dev * 1.0)
+        back = pr.sim.state(device=True).cpu().numpy()
+        assert np.array_equal(back, st)
+    finally:
+        pr.close()
+
+
+def test_divergence_and_conservation_on_gpu():
+    st = I.turbulence(48, seed=4)
+    pr = Pair((48, 48, 48), recon="ppm")
+    try:
+        pr.sim.set_state(st)
+        d0 = pr.sim.diagnostics()
+        o0 = oracle.diagnostics(pr.cfg, st)
+        assert np.allclose(d0[:8], o0[:8], rtol=1e-13, atol=1e-13)
+        pr.sim.run(20)
+        d1 = pr.sim.diagnostics()
+        bmax = np.abs(st[5 * 48 ** 3:]).max() * 48
+        _say(f"  max|divB| {d1[8]:.3e} (field/dx {bmax:.3e})")
+        assert d1[8] < 1e-12 * bmax
+        assert abs(d1[0] - d0[0]) < 1e-13 * d0[0]
+        assert abs(d1[4] - d0[4]) < 1e-13 * d0[4]
+        assert np.all(np.abs(d1[1:4] - d0[1:4]) < 1e-13 * d0[0])
+        assert np.all(np.abs(d1[5:8] - d0[5:8]) < 1e-13)
+    finally:
+        pr.close()
+
+
+def test_nonfinite_state_is_reported():
+    st = random_mhd((8, 8, 8), 1)
+    st[100] = np.nan
+    pr = Pair((8, 8, 8))
+    try:
+        pr.sim.set_state(st)
+        with pytest.raises(B.MhdError) as e:
+            pr.sim.dt_cfl()
+        assert e.value.code == -5
+    finally:
+        pr.close()

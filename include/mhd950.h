@@ -146,6 +146,22 @@ mhd_status mhd_dt_cfl(mhd_ctx* ctx, double* dt);
  *   of gas and dust.  Synchronises the stream. */
 mhd_status mhd_diagnostics(mhd_ctx* ctx, double* out, int n);
 
+/* Per-kernel timing for profiling (off by default).  With capacity > 0 the library
+ * records a pair of HIP events on the context's stream around each kernel launch,
+ * for up to `capacity` launches between reads (later launches are not recorded);
+ * capacity 0 turns timing off and releases the events.  Host-side events only: no
+ * device memory is allocated. */
+mhd_status mhd_timing_enable(mhd_ctx* ctx, int capacity);
+
+/* Synchronise the stream, then write for each kernel class q < nslot the summed
+ * device time in milliseconds ms[q] and the number of recorded launches launches[q]
+ * since the previous read, and clear the record.  Classes are numbered as
+ * mhd_timing_name lists them (nslot may be smaller than the number of classes). */
+mhd_status mhd_timing_read(mhd_ctx* ctx, double* ms, int* launches, int nslot);
+
+/* Name of kernel class q, or NULL past the last class. */
+const char* mhd_timing_name(int q);
+
 /* Release the host context (the workspace stays the caller's). */
 void mhd_destroy(mhd_ctx* ctx);
 

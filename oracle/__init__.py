@@ -65,6 +65,7 @@ def _lib():
         L = ctypes.CDLL(_LIB)
         dp = ctypes.POINTER(ctypes.c_double)
         cp = ctypes.POINTER(OrcCfg)
+        L.orc_num_threads.argtypes = []; L.orc_num_threads.restype = ctypes.c_int
         L.orc_state_len.argtypes = [cp]; L.orc_state_len.restype = ctypes.c_long
         L.orc_step.argtypes = [cp, dp, ctypes.c_double]; L.orc_step.restype = ctypes.c_int
         L.orc_dt_cfl.argtypes = [cp, dp]; L.orc_dt_cfl.restype = ctypes.c_double
@@ -108,6 +109,10 @@ def make_cfg(shape, length=(1.0, 1.0, 1.0), eos="adiabatic_mhd", gamma=5.0 / 3.0
     c.recon, c.riemann, c.integ = RECON[recon], RIEMANN[riemann], INTEG[integ]
     c.courant, c.hlld_eps = courant, hlld_eps
     return c
+
+
+def num_threads() -> int:
+    return int(_lib().orc_num_threads())
 
 
 def state_len(cfg: OrcCfg) -> int:

@@ -30,6 +30,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define NG 4 /* ghost width: PPM needs 3, constrained transport one more */
 
@@ -90,6 +93,15 @@ static double* zalloc(long n) { return (double*)calloc((size_t)n, sizeof(double)
 static int nvar_cells(const orc_cfg* c)
 {
     return c->eos == ORC_EOS_ADIABATIC_MHD ? 5 : 4 + 4 * c->ndust;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 long orc_state_len(const orc_cfg* c)

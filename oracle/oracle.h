@@ -42,6 +42,9 @@ typedef struct {
     double hlld_eps;         /* degeneracy tolerance of HLLD, relative to P_T* */
 } orc_cfg;
 
+/* Threads the OpenMP loops of the oracle use. */
+int orc_num_threads(void);
+
 /* Number of doubles in the canonical state of cfg. */
 long orc_state_len(const orc_cfg* cfg);
 

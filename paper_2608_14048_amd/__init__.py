@@ -10,4 +10,5 @@ use and its absence is an error.
 """
 from .binding import (MhdError, Sim, load_library, make_grid, make_physics, make_scheme,  # noqa: F401
                       mhd_create, mhd_destroy, mhd_diagnostics, mhd_dt_cfl, mhd_get_state,
-                      mhd_set_state, mhd_state_len, mhd_step, mhd_strerror, mhd_workspace_bytes)
+                      mhd_set_state, mhd_state_len, mhd_step, mhd_strerror, mhd_timing_enable,
+                      mhd_timing_name, mhd_timing_read, mhd_workspace_bytes)

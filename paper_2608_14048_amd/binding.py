@@ -77,8 +77,13 @@ def load_library(path: str = LIB_PATH):
     L.mhd_destroy.restype = None
     L.mhd_strerror.argtypes = [ctypes.c_int]
     L.mhd_strerror.restype = ctypes.c_char_p
+    L.mhd_timing_enable.argtypes = [vp, ctypes.c_int]
+    L.mhd_timing_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int), ctypes.c_int]
+    L.mhd_timing_name.argtypes = [ctypes.c_int]
+    L.mhd_timing_name.restype = ctypes.c_char_p
     for name in ("mhd_workspace_bytes", "mhd_create", "mhd_state_len", "mhd_set_state",
-                 "mhd_get_state", "mhd_step", "mhd_dt_cfl", "mhd_diagnostics"):
+                 "mhd_get_state", "mhd_step", "mhd_dt_cfl", "mhd_diagnostics",
+                 "mhd_timing_enable", "mhd_timing_read"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -193,6 +198,28 @@ def mhd_strerror(code: int) -> str:
     return load_library().mhd_strerror(code).decode()
 
 
+def mhd_timing_name(q: int):
+    r = load_library().mhd_timing_name(q)
+    return None if r is None else r.decode()
+
+
+def mhd_timing_enable(ctx: int, capacity: int):
+    _check(load_library().mhd_timing_enable(ctypes.c_void_p(ctx), int(capacity)), "mhd_timing_enable")
+
+
+def mhd_timing_read(ctx: int) -> dict:
+    """{kernel class: (summed ms, launches)} since the previous read."""
+    names = []
+    while mhd_timing_name(len(names)) is not None:
+        names.append(mhd_timing_name(len(names)))
+    ms = np.zeros(len(names))
+    cnt = (ctypes.c_int * len(names))()
+    _check(load_library().mhd_timing_read(ctypes.c_void_p(ctx),
+                                          ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          cnt, len(names)), "mhd_timing_read")
+    return {names[q]: (float(ms[q]), int(cnt[q])) for q in range(len(names)) if cnt[q] > 0}
+
+
 # ---------------------------------------------------------------------------------
 # convenience object: Mesh + Simulation in one (cf. the paper's user interface)
 # ---------------------------------------------------------------------------------
@@ -265,6 +292,13 @@ class Sim:
 
     def diagnostics(self) -> np.ndarray:
         return mhd_diagnostics(self.ctx, self.nq)
+
+    def timing(self, capacity: int):
+        """Record HIP events around up to `capacity` kernel launches (0 = off)."""
+        mhd_timing_enable(self.ctx, capacity)
+
+    def timing_read(self) -> dict:
+        return mhd_timing_read(self.ctx)
 
     def close(self):
         if getattr(self, "ctx", 0):

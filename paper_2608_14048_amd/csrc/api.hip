@@ -6,11 +6,36 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "../../include/mhd950.h"
 #include "launch.hpp"
 
 using namespace mhd;
+
+// kernel classes of the event timer
+enum TimerSlot {
+    T_MHD_PRIMS = 0,
+    T_MHD_FLUX_PRED,
+    T_MHD_FLUX_CORR,
+    T_MHD_EDGES,
+    T_MHD_UPDATE,
+    T_CFL,
+    T_DUST_PRIMS,
+    T_DUST_FLUX,
+    T_IMEX_STAGE1,
+    T_IMEX_STAGE2,
+    T_NSLOT
+};
+static const char* const kSlotNames[T_NSLOT] = {
+    "mhd_prims", "mhd_flux_predictor", "mhd_flux_corrector", "mhd_edges", "mhd_update",
+    "cfl", "dust_prims", "dust_flux", "imex_stage1", "imex_stage2"};
+
+struct EventTimer {
+    int cap = 0, used = 0;
+    std::vector<hipEvent_t> ev;  // 2 per launch
+    std::vector<int> slot;
+};
 
 struct mhd_ctx {
     mhd_grid grid;
@@ -32,6 +57,7 @@ struct mhd_ctx {
     double* scalars;  // [0] dt of the current state, [1..] diagnostics
     int cur;        // register holding the current state
     double cfl_scale;
+    EventTimer* timer;
 };
 
 namespace {
@@ -97,21 +123,54 @@ Layout layout(const mhd_grid* g, const mhd_physics* p)
 
 mhd_status dev(hipError_t e) { return e == hipSuccess ? MHD_OK : MHD_E_DEVICE; }
 
+// Event pair around one launch (no-op unless timing is on and capacity remains).
+struct Tick {
+    mhd_ctx* c;
+    int k;
+    Tick(mhd_ctx* ctx, int slot) : c(ctx), k(-1)
+    {
+        EventTimer* t = c->timer;
+        if (t && t->used < t->cap) {
+            k = t->used++;
+            t->slot[k] = slot;
+            (void)hipEventRecord(t->ev[2 * k], c->stream);
+        }
+    }
+    ~Tick()
+    {
+        if (k >= 0) (void)hipEventRecord(c->timer->ev[2 * k + 1], c->stream);
+    }
+};
+
 // Compute the CFL step of the current state into scalars[0].
 mhd_status refresh_cfl(mhd_ctx* c)
 {
     const double* U = c->reg[c->cur];
+    Tick t(c, T_CFL);
     if (c->is_mhd) return dev(launch_cfl_mhd(c->geo, c->mp, U, c->partial, c->scalars, c->cfl_scale, c->stream));
     return dev(launch_cfl_dust(c->geo, c->dp, U, c->partial, c->scalars, c->cfl_scale, c->stream));
 }
 
 mhd_status mhd_stage(mhd_ctx* c, int recon, const double* in, const double* base, double* out,
-                     StageCoef co)
+                     StageCoef co, int flux_slot)
 {
-    hipError_t e = launch_mhd_prims(c->geo, c->mp, in, c->W, c->stream);
-    if (e == hipSuccess) e = launch_mhd_fluxes(c->geo, c->mp, recon, c->scheme.riemann, c->W, in, c->F, c->stream);
-    if (e == hipSuccess) e = launch_mhd_edges(c->geo, c->W, c->F, c->E, c->stream);
-    if (e == hipSuccess) e = launch_mhd_update(c->geo, c->mp, in, base, c->F, c->E, out, co, c->stream);
+    hipError_t e;
+    {
+        Tick t(c, T_MHD_PRIMS);
+        e = launch_mhd_prims(c->geo, c->mp, in, c->W, c->stream);
+    }
+    for (int d = 0; d < 3 && e == hipSuccess; ++d) {
+        Tick t(c, flux_slot);
+        e = launch_mhd_flux_dir(c->geo, c->mp, recon, c->scheme.riemann, d, c->W, in, c->F, c->stream);
+    }
+    if (e == hipSuccess) {
+        Tick t(c, T_MHD_EDGES);
+        e = launch_mhd_edges(c->geo, c->W, c->F, c->E, c->stream);
+    }
+    if (e == hipSuccess) {
+        Tick t(c, T_MHD_UPDATE);
+        e = launch_mhd_update(c->geo, c->mp, in, base, c->F, c->E, out, co, c->stream);
+    }
     return dev(e);
 }
 
@@ -123,17 +182,17 @@ mhd_status step_mhd(mhd_ctx* c, double dt)
     switch (c->scheme.integ) {
     case MHD_INT_VL2:
         // predictor: donor cell, half step; corrector: configured recon, full step from U*
-        st = mhd_stage(c, MHD_RECON_DC, A, A, B, StageCoef{0.0, 1.0, 0.5 * dt});
+        st = mhd_stage(c, MHD_RECON_DC, A, A, B, StageCoef{0.0, 1.0, 0.5 * dt}, T_MHD_FLUX_PRED);
         if (st != MHD_OK) return st;
-        st = mhd_stage(c, c->scheme.recon, B, A, A, StageCoef{0.0, 1.0, dt});
+        st = mhd_stage(c, c->scheme.recon, B, A, A, StageCoef{0.0, 1.0, dt}, T_MHD_FLUX_CORR);
         break;
     case MHD_INT_RK2:
-        st = mhd_stage(c, c->scheme.recon, A, A, B, StageCoef{0.0, 1.0, dt});
+        st = mhd_stage(c, c->scheme.recon, A, A, B, StageCoef{0.0, 1.0, dt}, T_MHD_FLUX_PRED);
         if (st != MHD_OK) return st;
-        st = mhd_stage(c, c->scheme.recon, B, A, A, StageCoef{0.5, 0.5, 0.5 * dt});
+        st = mhd_stage(c, c->scheme.recon, B, A, A, StageCoef{0.5, 0.5, 0.5 * dt}, T_MHD_FLUX_CORR);
         break;
     default:  // EULER1
-        st = mhd_stage(c, c->scheme.recon, A, A, B, StageCoef{0.0, 1.0, dt});
+        st = mhd_stage(c, c->scheme.recon, A, A, B, StageCoef{0.0, 1.0, dt}, T_MHD_FLUX_CORR);
         c->cur = 1 - c->cur;
         break;
     }
@@ -145,12 +204,26 @@ mhd_status step_dust(mhd_ctx* c, double dt)
     double* u = c->reg[c->cur];
     double* U1 = c->reg[1 - c->cur];
     const int recon = c->scheme.recon;
-    hipError_t e = launch_dust_prims(c->geo, c->dp, u, c->W, c->stream);
-    if (e == hipSuccess) e = launch_dust_fluxes(c->geo, c->dp, recon, c->W, c->F, c->stream);
-    if (e == hipSuccess) e = launch_imex_stage1(c->geo, c->dp, u, c->F, U1, dt, c->stream);
-    if (e == hipSuccess) e = launch_dust_prims(c->geo, c->dp, U1, c->W, c->stream);
-    if (e == hipSuccess) e = launch_dust_fluxes(c->geo, c->dp, recon, c->W, c->F, c->stream);
-    if (e == hipSuccess) e = launch_imex_stage2(c->geo, c->dp, u, U1, c->F, dt, c->stream);
+    hipError_t e = hipSuccess;
+    for (int stage = 0; stage < 2 && e == hipSuccess; ++stage) {
+        const double* src = stage == 0 ? u : U1;
+        {
+            Tick t(c, T_DUST_PRIMS);
+            e = launch_dust_prims(c->geo, c->dp, src, c->W, c->stream);
+        }
+        if (e == hipSuccess) {
+            Tick t(c, T_DUST_FLUX);
+            e = launch_dust_fluxes(c->geo, c->dp, recon, c->W, c->F, c->stream);
+        }
+        if (e != hipSuccess) break;
+        if (stage == 0) {
+            Tick t(c, T_IMEX_STAGE1);
+            e = launch_imex_stage1(c->geo, c->dp, u, c->F, U1, dt, c->stream);
+        } else {
+            Tick t(c, T_IMEX_STAGE2);
+            e = launch_imex_stage2(c->geo, c->dp, u, U1, c->F, dt, c->stream);
+        }
+    }
     return dev(e);
 }
 
@@ -311,6 +384,67 @@ mhd_status mhd_diagnostics(mhd_ctx* c, double* out, int n)
     return MHD_OK;
 }
 
-void mhd_destroy(mhd_ctx* c) { delete c; }
+static void timer_free(mhd_ctx* c)
+{
+    if (!c->timer) return;
+    for (hipEvent_t e : c->timer->ev) (void)hipEventDestroy(e);
+    delete c->timer;
+    c->timer = nullptr;
+}
+
+mhd_status mhd_timing_enable(mhd_ctx* c, int capacity)
+{
+    if (!c || capacity < 0) return MHD_E_INVAL;
+    if (c->timer) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        timer_free(c);
+        if (e != hipSuccess) return MHD_E_DEVICE;
+    }
+    if (capacity == 0) return MHD_OK;
+    EventTimer* t = new (std::nothrow) EventTimer;
+    if (!t) return MHD_E_NOMEM;
+    t->cap = capacity;
+    t->ev.resize(2 * (size_t)capacity);
+    t->slot.resize(capacity);
+    for (auto& e : t->ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            delete t;
+            return MHD_E_DEVICE;
+        }
+    c->timer = t;
+    return MHD_OK;
+}
+
+mhd_status mhd_timing_read(mhd_ctx* c, double* ms, int* launches, int nslot)
+{
+    if (!c || !ms || !launches || nslot < 0) return MHD_E_INVAL;
+    for (int q = 0; q < nslot; ++q) {
+        ms[q] = 0.0;
+        launches[q] = 0;
+    }
+    if (!c->timer) return MHD_OK;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return MHD_E_DEVICE;
+    EventTimer* t = c->timer;
+    for (int k = 0; k < t->used; ++k) {
+        float f = 0.0f;
+        if (hipEventElapsedTime(&f, t->ev[2 * k], t->ev[2 * k + 1]) != hipSuccess) return MHD_E_DEVICE;
+        const int q = t->slot[k];
+        if (q < nslot) {
+            ms[q] += f;
+            launches[q] += 1;
+        }
+    }
+    t->used = 0;
+    return MHD_OK;
+}
+
+const char* mhd_timing_name(int q) { return (q >= 0 && q < T_NSLOT) ? kSlotNames[q] : nullptr; }
+
+void mhd_destroy(mhd_ctx* c)
+{
+    if (!c) return;
+    timer_free(c);
+    delete c;
+}
 
 }  // extern "C"

@@ -24,8 +24,8 @@ struct DustParams {
 hipError_t launch_mhd_prims(const Geo& g, const MhdParams& p, const double* U, double* W,
                             hipStream_t s);
 // F: 7 fields per direction, dir-major (mass, Mx, My, Mz, energy, E_t1, E_t2).
-hipError_t launch_mhd_fluxes(const Geo& g, const MhdParams& p, int recon, int riemann,
-                             const double* W, const double* U, double* F, hipStream_t s);
+hipError_t launch_mhd_flux_dir(const Geo& g, const MhdParams& p, int recon, int riemann, int dir,
+                               const double* W, const double* U, double* F, hipStream_t s);
 hipError_t launch_mhd_edges(const Geo& g, const double* W, const double* F, double* E,
                             hipStream_t s);
 hipError_t launch_mhd_update(const Geo& g, const MhdParams& p, const double* in,

@@ -193,28 +193,31 @@ hipError_t launch_mhd_prims(const Geo& g, const MhdParams& p, const double* U, d
 }
 
 template <int RECON, int RS>
-static hipError_t flux_all(const Geo& g, const MhdParams& p, const double* W, const double* U,
-                           double* F, hipStream_t s)
+static hipError_t flux_dir(const Geo& g, const MhdParams& p, int dir, const double* W,
+                           const double* U, double* F, hipStream_t s)
 {
     const long long n = g.n;
     const dim3 gr(blocks_for(n)), bl(kBlock);
-    hipLaunchKernelGGL((k_mhd_flux<0, RECON, RS>), gr, bl, 0, s, g, p, W, U + 5 * n, F);
-    hipLaunchKernelGGL((k_mhd_flux<1, RECON, RS>), gr, bl, 0, s, g, p, W, U + 6 * n, F + 7 * n);
-    hipLaunchKernelGGL((k_mhd_flux<2, RECON, RS>), gr, bl, 0, s, g, p, W, U + 7 * n, F + 14 * n);
+    if (dir == 0)
+        hipLaunchKernelGGL((k_mhd_flux<0, RECON, RS>), gr, bl, 0, s, g, p, W, U + 5 * n, F);
+    else if (dir == 1)
+        hipLaunchKernelGGL((k_mhd_flux<1, RECON, RS>), gr, bl, 0, s, g, p, W, U + 6 * n, F + 7 * n);
+    else
+        hipLaunchKernelGGL((k_mhd_flux<2, RECON, RS>), gr, bl, 0, s, g, p, W, U + 7 * n, F + 14 * n);
     return hipGetLastError();
 }
 
-hipError_t launch_mhd_fluxes(const Geo& g, const MhdParams& p, int recon, int riemann,
-                             const double* W, const double* U, double* F, hipStream_t s)
+hipError_t launch_mhd_flux_dir(const Geo& g, const MhdParams& p, int recon, int riemann, int dir,
+                               const double* W, const double* U, double* F, hipStream_t s)
 {
     if (riemann == 1) {
-        if (recon == 0) return flux_all<0, 1>(g, p, W, U, F, s);
-        if (recon == 1) return flux_all<1, 1>(g, p, W, U, F, s);
-        return flux_all<2, 1>(g, p, W, U, F, s);
+        if (recon == 0) return flux_dir<0, 1>(g, p, dir, W, U, F, s);
+        if (recon == 1) return flux_dir<1, 1>(g, p, dir, W, U, F, s);
+        return flux_dir<2, 1>(g, p, dir, W, U, F, s);
     }
-    if (recon == 0) return flux_all<0, 0>(g, p, W, U, F, s);
-    if (recon == 1) return flux_all<1, 0>(g, p, W, U, F, s);
-    return flux_all<2, 0>(g, p, W, U, F, s);
+    if (recon == 0) return flux_dir<0, 0>(g, p, dir, W, U, F, s);
+    if (recon == 1) return flux_dir<1, 0>(g, p, dir, W, U, F, s);
+    return flux_dir<2, 0>(g, p, dir, W, U, F, s);
 }
 
 hipError_t launch_mhd_edges(const Geo& g, const double* W, const double* F, double* E,

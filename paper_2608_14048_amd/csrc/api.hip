@@ -15,11 +15,10 @@ using namespace mhd;
 
 // kernel classes of the event timer
 enum TimerSlot {
-    T_MHD_PRIMS = 0,
-    T_MHD_FLUX_PRED,
+    T_MHD_FLUX_PRED = 0,
     T_MHD_FLUX_CORR,
-    T_MHD_EDGES,
-    T_MHD_UPDATE,
+    T_MHD_CT_PRED,
+    T_MHD_CT_CORR,
     T_CFL,
     T_DUST_PRIMS,
     T_DUST_FLUX,
@@ -28,8 +27,8 @@ enum TimerSlot {
     T_NSLOT
 };
 static const char* const kSlotNames[T_NSLOT] = {
-    "mhd_prims", "mhd_flux_predictor", "mhd_flux_corrector", "mhd_edges", "mhd_update",
-    "cfl", "dust_prims", "dust_flux", "imex_stage1", "imex_stage2"};
+    "mhd_flux_predictor", "mhd_flux_corrector", "mhd_ct_update_predictor",
+    "mhd_ct_update_corrector", "cfl", "dust_prims", "dust_flux", "imex_stage1", "imex_stage2"};
 
 struct EventTimer {
     int cap = 0, used = 0;
@@ -49,10 +48,11 @@ struct mhd_ctx {
     int nvar;       // fields of the canonical state
     long long n;    // cells
     // workspace views
-    double* reg[2]; // state registers (canonical layout each)
-    double* W;      // primitives
+    double* reg[3]; // state registers (canonical layout each; MHD rotates all three)
+    double* W;      // primitives (dust)
     double* F;      // face fluxes, 3 direction blocks
-    double* E;      // edge EMFs (MHD)
+    double* Rc;     // cell-centred E = -v x B (MHD)
+    FusedGrid fg;   // tiling of the MHD stage kernels
     double* partial;
     double* scalars;  // [0] dt of the current state, [1..] diagnostics
     int cur;        // register holding the current state
@@ -65,8 +65,32 @@ namespace {
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t reg, W, F, E, partial, scalars, total;
+    size_t reg, nreg, W, F, Rc, partial, scalars, total;
 };
+
+// z planes per workgroup of the MHD kernels: about 2048 workgroups on large grids.
+int choose_kz(const mhd_grid* g)
+{
+    const long long tiles = (long long)((g->nx + 63) / 64) * ((g->ny + 3) / 4);
+    const long long want = (2048 + tiles - 1) / tiles;
+    int kz = (int)((g->nz + want - 1) / want);
+    if (kz < 4) kz = 4;
+    if (kz > g->nz) kz = g->nz;
+    return kz;
+}
+
+Geo make_geo(const mhd_grid* grid)
+{
+    Geo g;
+    g.nx = grid->nx; g.ny = grid->ny; g.nz = grid->nz;
+    g.n = (long long)grid->nx * grid->ny * grid->nz;
+    const int ns[3] = {grid->nx, grid->ny, grid->nz};
+    for (int a = 0; a < 3; ++a) {
+        g.dx[a] = grid->length[a] / ns[a];
+        g.inv_dx[a] = 1.0 / g.dx[a];
+    }
+    return g;
+}
 
 int state_fields(const mhd_physics* p)
 {
@@ -79,7 +103,8 @@ mhd_status validate(const mhd_grid* g, const mhd_physics* p, const mhd_scheme* s
     if (g->nx < 1 || g->ny < 1 || g->nz < 1) return MHD_E_INVAL;
     for (int a = 0; a < 3; ++a)
         if (!(g->length[a] > 0.0) || !std::isfinite(g->length[a])) return MHD_E_INVAL;
-    if ((long long)g->nx * g->ny * g->nz > (1LL << 34)) return MHD_E_INVAL;
+    // every field is addressed with 32-bit byte offsets: below 4 GiB, i.e. < 2^29 cells
+    if ((long long)g->nx * g->ny * g->nz >= (1LL << 29)) return MHD_E_UNSUPPORTED;
     if (!(s->courant > 0.0) || !std::isfinite(s->courant)) return MHD_E_INVAL;
     if (s->prec != MHD_PREC_FP64) return MHD_E_UNSUPPORTED;
     if (s->recon < MHD_RECON_DC || s->recon > MHD_RECON_PPM) return MHD_E_UNSUPPORTED;
@@ -111,13 +136,16 @@ Layout layout(const mhd_grid* g, const mhd_physics* p)
     const bool is_mhd = p->eos == MHD_EOS_ADIABATIC_MHD;
     Layout L;
     L.reg = align256(field * nv);
-    L.W = align256(field * nv);
+    L.nreg = is_mhd ? 3 : 2;
+    L.W = is_mhd ? 0 : align256(field * nv);
     L.F = align256(field * (is_mhd ? 21 : 3 * nv));
-    L.E = is_mhd ? align256(field * 3) : 0;
-    const size_t nb = blocks_for(n);
+    L.Rc = is_mhd ? align256(field * 3) : 0;
+    size_t nb = blocks_for(n);
+    const size_t nf = fused_grid(make_geo(g), choose_kz(g)).nblk;
+    if (nf > nb) nb = nf;
     L.partial = align256(nb * sizeof(double) * (size_t)diag_count(MHD_MAX_DUST));
     L.scalars = align256(sizeof(double) * 64);
-    L.total = 2 * L.reg + L.W + L.F + L.E + L.partial + L.scalars;
+    L.total = L.nreg * L.reg + L.W + L.F + L.Rc + L.partial + L.scalars;
     return L;
 }
 
@@ -151,49 +179,49 @@ mhd_status refresh_cfl(mhd_ctx* c)
     return dev(launch_cfl_dust(c->geo, c->dp, U, c->partial, c->scalars, c->cfl_scale, c->stream));
 }
 
+// One stage: fluxes of `in`, then out = g0 in + g1 base + bdt L(in) (and, if last,
+// the CFL step of out into scalars[0]).
 mhd_status mhd_stage(mhd_ctx* c, int recon, const double* in, const double* base, double* out,
-                     StageCoef co, int flux_slot)
+                     StageCoef co, bool corrector, bool last)
 {
     hipError_t e;
     {
-        Tick t(c, T_MHD_PRIMS);
-        e = launch_mhd_prims(c->geo, c->mp, in, c->W, c->stream);
-    }
-    for (int d = 0; d < 3 && e == hipSuccess; ++d) {
-        Tick t(c, flux_slot);
-        e = launch_mhd_flux_dir(c->geo, c->mp, recon, c->scheme.riemann, d, c->W, in, c->F, c->stream);
+        Tick t(c, corrector ? T_MHD_FLUX_CORR : T_MHD_FLUX_PRED);
+        e = launch_mhd_flux3(c->geo, c->mp, c->fg, recon, c->scheme.riemann, in, c->F, c->Rc, c->stream);
     }
     if (e == hipSuccess) {
-        Tick t(c, T_MHD_EDGES);
-        e = launch_mhd_edges(c->geo, c->W, c->F, c->E, c->stream);
-    }
-    if (e == hipSuccess) {
-        Tick t(c, T_MHD_UPDATE);
-        e = launch_mhd_update(c->geo, c->mp, in, base, c->F, c->E, out, co, c->stream);
+        Tick t(c, corrector ? T_MHD_CT_CORR : T_MHD_CT_PRED);
+        e = launch_mhd_ct_update(c->geo, c->mp, c->fg, in, base, c->F, c->Rc, out, co, c->partial,
+                                 last ? c->scalars : nullptr, c->cfl_scale, c->stream);
     }
     return dev(e);
 }
 
+// The registers rotate: the state S = reg[cur]; stages write only to the two others.
 mhd_status step_mhd(mhd_ctx* c, double dt)
 {
-    double* A = c->reg[c->cur];
-    double* B = c->reg[1 - c->cur];
+    const int s0 = c->cur, s1 = (c->cur + 1) % 3, s2 = (c->cur + 2) % 3;
+    double* S = c->reg[s0];
+    double* A = c->reg[s1];
+    double* B = c->reg[s2];
     mhd_status st;
     switch (c->scheme.integ) {
     case MHD_INT_VL2:
         // predictor: donor cell, half step; corrector: configured recon, full step from U*
-        st = mhd_stage(c, MHD_RECON_DC, A, A, B, StageCoef{0.0, 1.0, 0.5 * dt}, T_MHD_FLUX_PRED);
+        st = mhd_stage(c, MHD_RECON_DC, S, S, A, StageCoef{0.0, 1.0, 0.5 * dt}, false, false);
         if (st != MHD_OK) return st;
-        st = mhd_stage(c, c->scheme.recon, B, A, A, StageCoef{0.0, 1.0, dt}, T_MHD_FLUX_CORR);
+        st = mhd_stage(c, c->scheme.recon, A, S, B, StageCoef{0.0, 1.0, dt}, true, true);
+        c->cur = s2;
         break;
     case MHD_INT_RK2:
-        st = mhd_stage(c, c->scheme.recon, A, A, B, StageCoef{0.0, 1.0, dt}, T_MHD_FLUX_PRED);
+        st = mhd_stage(c, c->scheme.recon, S, S, A, StageCoef{0.0, 1.0, dt}, false, false);
         if (st != MHD_OK) return st;
-        st = mhd_stage(c, c->scheme.recon, B, A, A, StageCoef{0.5, 0.5, 0.5 * dt}, T_MHD_FLUX_CORR);
+        st = mhd_stage(c, c->scheme.recon, A, S, B, StageCoef{0.5, 0.5, 0.5 * dt}, true, true);
+        c->cur = s2;
         break;
     default:  // EULER1
-        st = mhd_stage(c, c->scheme.recon, A, A, B, StageCoef{0.0, 1.0, dt}, T_MHD_FLUX_CORR);
-        c->cur = 1 - c->cur;
+        st = mhd_stage(c, c->scheme.recon, S, S, A, StageCoef{0.0, 1.0, dt}, true, true);
+        c->cur = s1;
         break;
     }
     return st;
@@ -276,14 +304,8 @@ mhd_status mhd_create(const mhd_grid* grid, const mhd_physics* phys, const mhd_s
     c->nvar = state_fields(phys);
     c->n = (long long)grid->nx * grid->ny * grid->nz;
 
-    Geo& g = c->geo;
-    g.nx = grid->nx; g.ny = grid->ny; g.nz = grid->nz;
-    g.n = c->n;
-    const int ns[3] = {grid->nx, grid->ny, grid->nz};
-    for (int a = 0; a < 3; ++a) {
-        g.dx[a] = grid->length[a] / ns[a];
-        g.inv_dx[a] = 1.0 / g.dx[a];
-    }
+    c->geo = make_geo(grid);
+    c->fg = fused_grid(c->geo, choose_kz(grid));
     c->mp.gamma = phys->gamma;
     c->mp.gm1inv = 1.0 / (phys->gamma - 1.0);
     c->mp.rho_floor = phys->rho_floor;
@@ -302,11 +324,13 @@ mhd_status mhd_create(const mhd_grid* grid, const mhd_physics* phys, const mhd_s
     c->cfl_scale = scheme->courant * cmax;
 
     char* base = (char*)device_workspace;
-    c->reg[0] = (double*)base; base += L.reg;
-    c->reg[1] = (double*)base; base += L.reg;
-    c->W = (double*)base; base += L.W;
+    for (size_t r = 0; r < 3; ++r) {
+        c->reg[r] = r < L.nreg ? (double*)base : nullptr;
+        if (r < L.nreg) base += L.reg;
+    }
+    c->W = L.W ? (double*)base : nullptr; base += L.W;
     c->F = (double*)base; base += L.F;
-    c->E = L.E ? (double*)base : nullptr; base += L.E;
+    c->Rc = L.Rc ? (double*)base : nullptr; base += L.Rc;
     c->partial = (double*)base; base += L.partial;
     c->scalars = (double*)base;
     c->cur = 0;
@@ -352,7 +376,8 @@ mhd_status mhd_step(mhd_ctx* c, double dt)
 {
     if (!c) return MHD_E_INVAL;
     if (!(dt > 0.0) || !std::isfinite(dt)) return MHD_E_INVAL;
-    mhd_status st = c->is_mhd ? step_mhd(c, dt) : step_dust(c, dt);
+    if (c->is_mhd) return step_mhd(c, dt);  // the last stage reduces the CFL step itself
+    mhd_status st = step_dust(c, dt);
     if (st != MHD_OK) return st;
     return refresh_cfl(c);
 }

@@ -55,6 +55,18 @@ __device__ __forceinline__ double min_nan(double a, double b)
     return a < b ? a : b;
 }
 
+// Loads and stores at a 32-bit byte offset from a uniform base pointer: the address is
+// formed by the memory unit (scalar base + vector offset), not by 64-bit vector math.
+// Fields must stay below 4 GiB (checked when a context is created).
+__device__ __forceinline__ double ld_at(const double* __restrict__ base, unsigned int boff)
+{
+    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + boff);
+}
+__device__ __forceinline__ void st_at(double* base, unsigned int boff, double v)
+{
+    *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + boff) = v;
+}
+
 // Stage combination out = g0*in + g1*base + bdt*L of eq. (two_register).
 struct StageCoef {
     double g0, g1, bdt;

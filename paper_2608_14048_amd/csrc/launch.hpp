@@ -19,18 +19,24 @@ struct DustParams {
     double ts[kMaxDust];
 };
 
-// ---- adiabatic MHD ----
-// U: 8 fields (rho, M1..3, E, b1..3) of the stage input; W: 8 primitive fields.
-hipError_t launch_mhd_prims(const Geo& g, const MhdParams& p, const double* U, double* W,
-                            hipStream_t s);
-// F: 7 fields per direction, dir-major (mass, Mx, My, Mz, energy, E_t1, E_t2).
-hipError_t launch_mhd_flux_dir(const Geo& g, const MhdParams& p, int recon, int riemann, int dir,
-                               const double* W, const double* U, double* F, hipStream_t s);
-hipError_t launch_mhd_edges(const Geo& g, const double* W, const double* F, double* E,
-                            hipStream_t s);
-hipError_t launch_mhd_update(const Geo& g, const MhdParams& p, const double* in,
-                             const double* base, const double* F, const double* E,
-                             double* out, StageCoef coef, hipStream_t s);
+// ---- adiabatic MHD (z-marching tile kernels) ----
+struct FusedGrid {
+    int kz;                       // z planes per workgroup
+    unsigned int ntx, nty, ntz;   // tiles along x, y, z
+    unsigned int nblk;            // workgroups
+};
+FusedGrid fused_grid(const Geo& g, int kz);
+// U: 8 fields (rho, M1..3, E, b1..3) of the stage input.
+// F: 7 fields per direction, dir-major (mass, Mx, My, Mz, energy, E_t1, E_t2); Rc: 3
+// fields of the cell E = -v x B.
+hipError_t launch_mhd_flux3(const Geo& g, const MhdParams& p, const FusedGrid& fg, int recon,
+                            int riemann, const double* U, double* F, double* Rc, hipStream_t s);
+// out = g0 in + g1 base + bdt L; out must not alias in or base.  With dt_out the CFL
+// step of out (times cfl_scale) is reduced into dt_out via one partial per workgroup.
+hipError_t launch_mhd_ct_update(const Geo& g, const MhdParams& p, const FusedGrid& fg,
+                                const double* in, const double* base, const double* F,
+                                const double* Rc, double* out, StageCoef coef, double* partial,
+                                double* dt_out, double cfl_scale, hipStream_t s);
 
 // ---- CFL and diagnostics ----
 // partial: ceil(n/kBlock) doubles; dt_out: 1 double on the device.
@@ -38,6 +44,9 @@ hipError_t launch_cfl_mhd(const Geo& g, const MhdParams& p, const double* U, dou
                           double* dt_out, double scale, hipStream_t s);
 hipError_t launch_cfl_dust(const Geo& g, const DustParams& p, const double* U,
                            double* partial, double* dt_out, double scale, hipStream_t s);
+// out[0] = scale * (NaN-propagating) min of partial[0..m)
+hipError_t launch_min_final(const double* partial, long long m, double scale, double* out,
+                            hipStream_t s);
 // partial: ceil(n/kBlock) * nq doubles; out: nq doubles on the device.
 int diag_count(int ndust);
 hipError_t launch_diag(const Geo& g, int mhd, int ndust, const double* U, double* partial,

@@ -80,6 +80,14 @@ __device__ __forceinline__ void face_states<1>(const double* s, double& aL, doub
     aR = s[3] - 0.5 * slope_vl(s[2], s[3], s[4]);
 }
 
+// Colella-Woodward interface value between cells a0 and a1 from their limited slopes
+// (the fourth-order average, monotonised through the slopes).
+__device__ __forceinline__ double cw_interface(double a0, double a1, double m0, double m1)
+{
+    constexpr double kSixth = 1.0 / 6.0;
+    return a0 + 0.5 * (a1 - a0) - (m1 - m0) * kSixth;
+}
+
 // PPM: the three interface values around the two cells next to the face are shared.
 template <>
 __device__ __forceinline__ void face_states<2>(const double* s, double& aL, double& aR)
@@ -88,11 +96,9 @@ __device__ __forceinline__ void face_states<2>(const double* s, double& aL, doub
     const double m2 = cw_slope(s[1], s[2], s[3]);
     const double m3 = cw_slope(s[2], s[3], s[4]);
     const double m4 = cw_slope(s[3], s[4], s[5]);
-    const double sixth = 1.0 / 6.0;
-    const double i0 = s[1] + 0.5 * (s[2] - s[1]) - (m2 - m1) / 6.0;  // a_{f-3/2}
-    const double i1 = s[2] + 0.5 * (s[3] - s[2]) - (m3 - m2) / 6.0;  // a_{f-1/2}
-    const double i2 = s[3] + 0.5 * (s[4] - s[3]) - (m4 - m3) / 6.0;  // a_{f+1/2}
-    (void)sixth;
+    const double i0 = cw_interface(s[1], s[2], m1, m2);  // a_{f-3/2}
+    const double i1 = cw_interface(s[2], s[3], m2, m3);  // a_{f-1/2}
+    const double i2 = cw_interface(s[3], s[4], m3, m4);  // a_{f+1/2}
     double lo = i0, hi = i1;
     cw_limit(s[2], lo, hi);
     aL = hi;
@@ -109,9 +115,10 @@ __device__ __forceinline__ void face_states<2>(const double* s, double& aL, doub
 // Fast magnetosonic speed along a direction with field component bd; b2 = |B|^2.
 __device__ __forceinline__ double fast_speed(double gam, double d, double p, double b2, double bd)
 {
-    const double a2 = gam * p / d;
-    const double s = a2 + b2 / d;
-    const double disc = fmax(s * s - 4.0 * a2 * bd * bd / d, 0.0);
+    const double id = 1.0 / d;
+    const double a2 = gam * p * id;
+    const double s = a2 + b2 * id;
+    const double disc = fmax(s * s - 4.0 * a2 * (bd * bd) * id, 0.0);
     return sqrt(0.5 * (s + sqrt(disc)));
 }
 

@@ -111,6 +111,13 @@ __global__ __launch_bounds__(kBlock) void k_min_final(const double* __restrict__
     if (threadIdx.x == 0) out[0] = scale * r;
 }
 
+hipError_t launch_min_final(const double* partial, long long m, double scale, double* out,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(k_min_final, dim3(1), dim3(kBlock), 0, s, partial, m, scale, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_cfl_mhd(const Geo& g, const MhdParams& p, const double* U, double* partial,
                           double* dt_out, double scale, hipStream_t s)
 {

@@ -23,7 +23,8 @@ struct DustParams {
 struct FusedGrid {
     int kz;                       // z planes per workgroup
     unsigned int ntx, nty, ntz;   // tiles along x, y, z
-    unsigned int nblk;            // workgroups
+    unsigned int nblk;            // workgroups of the flux kernel
+    unsigned int nty2, nblk2;     // tiles along y and workgroups of the CT/update kernel
 };
 FusedGrid fused_grid(const Geo& g, int kz);
 // U: 8 fields (rho, M1..3, E, b1..3) of the stage input.

@@ -27,8 +27,9 @@ namespace mhd {
 
 namespace {
 
-constexpr int TX = 64;  // lanes along x
-constexpr int TY = 4;   // waves along y
+constexpr int TX = 64;   // lanes along x
+constexpr int TY = 4;    // waves along y (flux kernel)
+constexpr int TY2 = 8;   // waves along y (CT/update kernel: one halo row per 8 rows)
 
 // Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous run of tiles
 // so neighbouring tiles (which share halo rows) share an L2.
@@ -355,20 +356,20 @@ struct CtArgs {
 // CFL: reduce the time step of the output.  IN: the stage reads its input register
 // (g0 != 0 or a gas acceleration is set); otherwise only the base register is read.
 template <bool CFL, bool IN>
-__global__ __launch_bounds__(TX* TY) void k_ct_update(Geo g, MhdParams P, CtArgs a, int kz,
+__global__ __launch_bounds__(TX* TY2) void k_ct_update(Geo g, MhdParams P, CtArgs a, int kz,
                                                      unsigned int ntx, unsigned int nty,
                                                      unsigned int nblk)
 {
     // edges held for the tile: E_z on plane k, E_x / E_y on levels k-1/2 (slot lv^1)
-    // and k+1/2 (slot lv); index ranges i in [0, TX], j in [0, TY]
-    __shared__ double sEz[TY + 1][TX + 1];
-    __shared__ double sEx[2][TY + 1][TX + 1];
-    __shared__ double sEy[2][TY + 1][TX + 1];
-    __shared__ double sMin[TX * TY / 64];
+    // and k+1/2 (slot lv); index ranges i in [0, TX], j in [0, TY2]
+    __shared__ double sEz[TY2 + 1][TX + 1];
+    __shared__ double sEx[2][TY2 + 1][TX + 1];
+    __shared__ double sEy[2][TY2 + 1][TX + 1];
+    __shared__ double sMin[TX * TY2 / 64];
 
     const unsigned int bt = xcd_tile(blockIdx.x, nblk);
     const int x0 = (int)(bt % ntx) * TX;
-    const int y0 = (int)((bt / ntx) % nty) * TY;
+    const int y0 = (int)((bt / ntx) % nty) * TY2;
     const int k0 = (int)(bt / (ntx * nty)) * kz;
     const int k1 = min(k0 + kz, g.nz);
     const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
@@ -420,13 +421,13 @@ __global__ __launch_bounds__(TX* TY) void k_ct_update(Geo g, MhdParams P, CtArgs
     // level edges E_x, E_y at z-level zl - 1/2 for the tile (+1 ring on the high side)
     auto fill_level = [&](int slot, int zl) {
         const int zz = wrap_once(zl, g.nz);
-        for (int q = threadIdx.x; q < (TX + 1) * (TY + 1); q += TX * TY) {
+        for (int q = threadIdx.x; q < (TX + 1) * (TY2 + 1); q += TX * TY2) {
             const int r = q / (TX + 1), cc = q - r * (TX + 1);
             const int gx = x0 + cc, gy = y0 + r;
             if (gx > g.nx || gy > g.ny) continue;
             const int wx = gx == g.nx ? 0 : gx, wy = gy == g.ny ? 0 : gy;
             if (cc < TX && gx < g.nx) sEx[slot][r][cc] = edge_x(wx, wy, zz);
-            if (r < TY && gy < g.ny) sEy[slot][r][cc] = edge_y(wx, wy, zz);
+            if (r < TY2 && gy < g.ny) sEy[slot][r][cc] = edge_y(wx, wy, zz);
         }
     };
 
@@ -437,7 +438,7 @@ __global__ __launch_bounds__(TX* TY) void k_ct_update(Geo g, MhdParams P, CtArgs
 
     for (int k = k0; k < k1; ++k) {
         // edges: E_z on plane k, E_x / E_y on level k + 1/2
-        for (int q = threadIdx.x; q < (TX + 1) * (TY + 1); q += TX * TY) {
+        for (int q = threadIdx.x; q < (TX + 1) * (TY2 + 1); q += TX * TY2) {
             const int r = q / (TX + 1), cc = q - r * (TX + 1);
             const int gx = x0 + cc, gy = y0 + r;
             if (gx > g.nx || gy > g.ny) continue;
@@ -534,7 +535,7 @@ __global__ __launch_bounds__(TX* TY) void k_ct_update(Geo g, MhdParams P, CtArgs
         if (threadIdx.x == 0) {
             double r = sMin[0];
 #pragma unroll
-            for (int w = 1; w < TX * TY / 64; ++w) r = min_nan(r, sMin[w]);
+            for (int w = 1; w < TX * TY2 / 64; ++w) r = min_nan(r, sMin[w]);
             a.partial[blockIdx.x] = r;
         }
     }
@@ -552,6 +553,8 @@ FusedGrid fused_grid(const Geo& g, int kz)
     fg.nty = (unsigned int)((g.ny + TY - 1) / TY);
     fg.ntz = (unsigned int)((g.nz + kz - 1) / kz);
     fg.nblk = fg.ntx * fg.nty * fg.ntz;
+    fg.nty2 = (unsigned int)((g.ny + TY2 - 1) / TY2);
+    fg.nblk2 = fg.ntx * fg.nty2 * fg.ntz;
     return fg;
 }
 
@@ -584,20 +587,20 @@ hipError_t launch_mhd_ct_update(const Geo& g, const MhdParams& p, const FusedGri
 {
     CtArgs a{in, base, F, Rc, out, partial, coef};
     const bool use_in = coef.g0 != 0.0 || p.gacc[0] != 0.0 || p.gacc[1] != 0.0 || p.gacc[2] != 0.0;
-    const dim3 gr(fg.nblk), bl(TX * TY);
+    const dim3 gr(fg.nblk2), bl(TX * TY2);
     if (dt_out) {
         if (use_in)
-            hipLaunchKernelGGL((k_ct_update<true, true>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty, fg.nblk);
+            hipLaunchKernelGGL((k_ct_update<true, true>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty2, fg.nblk2);
         else
-            hipLaunchKernelGGL((k_ct_update<true, false>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty, fg.nblk);
+            hipLaunchKernelGGL((k_ct_update<true, false>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty2, fg.nblk2);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        return launch_min_final(partial, fg.nblk, cfl_scale, dt_out, s);
+        return launch_min_final(partial, fg.nblk2, cfl_scale, dt_out, s);
     }
     if (use_in)
-        hipLaunchKernelGGL((k_ct_update<false, true>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty, fg.nblk);
+        hipLaunchKernelGGL((k_ct_update<false, true>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty2, fg.nblk2);
     else
-        hipLaunchKernelGGL((k_ct_update<false, false>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty, fg.nblk);
+        hipLaunchKernelGGL((k_ct_update<false, false>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty2, fg.nblk2);
     return hipGetLastError();
 }
 

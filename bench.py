@@ -98,6 +98,41 @@ def cpu_baseline(n: int, state, max_seconds: float = 30.0):
                       f"({el:.1f} s, OpenMP over k-planes)"}
 
 
+def fp32_leg(n, state, warm_dts, dts, ref64):
+    """The FP32-bulk form (FP64 total energy) on the same workload and the same dt
+    sequence as the FP64 run (each step still reads its own CFL step, as in the FP64
+    loop); reports its throughput and the relative L1 difference of each conserved
+    class to the FP64 state after the same steps."""
+    import torch
+
+    from paper_2608_14048_amd import Sim
+
+    print("[bench] FP32-bulk leg", file=sys.stderr, flush=True)
+    sim = Sim((n, n, n), scheme=dict(recon="ppm", riemann="hlld", integ="vl2", courant=0.3,
+                                     prec="fp32_bulk"))
+    sim.set_state(state)
+    for dt in warm_dts:
+        sim.dt_cfl()
+        sim.step(dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for dt in dts:
+        sim.dt_cfl()
+        sim.step(dt)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    got = sim.state(device=True).reshape(8, -1)
+    ref = ref64.reshape(8, -1)
+    rows = {"rho": [0], "M": [1, 2, 3], "E": [4], "B": [5, 6, 7]}
+    l1 = {k: float((got[v] - ref[v]).abs().sum() / ref[v].abs().sum()) for k, v in rows.items()}
+    sim.close()
+    steps = len(dts)
+    return {"value": round(n ** 3 * steps / el / 1e6, 2), "unit": "Mzone-cycles/s",
+            "ms_per_step": round(el * 1e3 / steps, 4), "dtype": "f32 (E in f64)",
+            "l1_rel_vs_fp64": {k: float(f"{v:.3e}") for k, v in l1.items()},
+            "compared_after_steps": len(warm_dts) + steps}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +142,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=25.0)
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-bulk leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 2 GiB device copy three times (the calibration "
                          "launch for HBM byte counters)")
@@ -140,17 +176,23 @@ def main():
     sim = Sim((n, n, n), scheme=dict(recon="ppm", riemann="hlld", integ="vl2", courant=0.3))
     sim.set_state(state)
     print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    warm_dts = []
     for _ in range(args.warmup):
-        sim.step(sim.dt_cfl())
+        dt = sim.dt_cfl()
+        sim.step(dt)
+        warm_dts.append(dt)
     torch.cuda.synchronize()
     # events around every launch of the timed region (16 launches per step at most)
     sim.timing(capacity=32 * args.steps + 64)
     sim.timing_read()
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    dts = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        sim.step(sim.dt_cfl())
+        dt = sim.dt_cfl()
+        sim.step(dt)
+        dts.append(dt)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     times = sim.timing_read()
@@ -202,10 +244,12 @@ def main():
                               "frac": round(value * 1e6 * STEP_ALGO_BYTES / (HBM_PEAK_GBS * 1e9), 4)},
         "kernel_ms_per_step": kernel_ms,
     }
+    if not args.no_fp32:
+        out["fp32_bulk"] = fp32_leg(n, state, warm_dts, dts, sim.state(device=True))
+    sim.close()
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(n, state, args.cpu_seconds)
-    sim.close()
     print(json.dumps(out), flush=True)
 
 

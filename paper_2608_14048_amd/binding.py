@@ -20,7 +20,7 @@ EOS = {"adiabatic_mhd": 0, "isothermal_hydro": 1}
 RECON = {"dc": 0, "plm": 1, "ppm": 2}
 RIEMANN = {"hlle": 0, "hlld": 1}
 INTEG = {"vl2": 0, "rk2": 1, "imex2p": 2, "euler1": 3}
-PREC = {"fp64": 0}
+PREC = {"fp64": 0, "fp32_bulk": 1}
 
 STATUS = {0: "MHD_OK", -1: "MHD_E_INVAL", -2: "MHD_E_UNSUPPORTED", -3: "MHD_E_NOMEM",
           -4: "MHD_E_DEVICE", -5: "MHD_E_NONFINITE"}

@@ -47,11 +47,12 @@ struct mhd_ctx {
     bool is_mhd;
     int nvar;       // fields of the canonical state
     long long n;    // cells
+    bool fp32;      // FP32-bulk form of the MHD path
     // workspace views
-    double* reg[3]; // state registers (canonical layout each; MHD rotates all three)
+    void* reg[3];   // state registers (MHD rotates all three; see reg_view for the layout)
     double* W;      // primitives (dust)
-    double* F;      // face fluxes, 3 direction blocks
-    double* Rc;     // cell-centred E = -v x B (MHD)
+    void* F;        // face fluxes, 3 direction blocks (the path's real type)
+    void* Rc;       // cell-centred E = -v x B (MHD)
     FusedGrid fg;   // tiling of the MHD stage kernels
     double* partial;
     double* scalars;  // [0] dt of the current state, [1..] diagnostics
@@ -106,7 +107,8 @@ mhd_status validate(const mhd_grid* g, const mhd_physics* p, const mhd_scheme* s
     // every field is addressed with 32-bit byte offsets: below 4 GiB, i.e. < 2^29 cells
     if ((long long)g->nx * g->ny * g->nz >= (1LL << 29)) return MHD_E_UNSUPPORTED;
     if (!(s->courant > 0.0) || !std::isfinite(s->courant)) return MHD_E_INVAL;
-    if (s->prec != MHD_PREC_FP64) return MHD_E_UNSUPPORTED;
+    if (s->prec != MHD_PREC_FP64 && s->prec != MHD_PREC_FP32_BULK) return MHD_E_UNSUPPORTED;
+    if (s->prec == MHD_PREC_FP32_BULK && p->eos != MHD_EOS_ADIABATIC_MHD) return MHD_E_UNSUPPORTED;
     if (s->recon < MHD_RECON_DC || s->recon > MHD_RECON_PPM) return MHD_E_UNSUPPORTED;
     if (s->riemann != MHD_RS_HLLE && s->riemann != MHD_RS_HLLD) return MHD_E_UNSUPPORTED;
     if (p->eos == MHD_EOS_ADIABATIC_MHD) {
@@ -128,18 +130,21 @@ mhd_status validate(const mhd_grid* g, const mhd_physics* p, const mhd_scheme* s
     return MHD_OK;
 }
 
-Layout layout(const mhd_grid* g, const mhd_physics* p)
+Layout layout(const mhd_grid* g, const mhd_physics* p, const mhd_scheme* sc)
 {
     const long long n = (long long)g->nx * g->ny * g->nz;
     const size_t field = (size_t)n * sizeof(double);
     const int nv = state_fields(p);
     const bool is_mhd = p->eos == MHD_EOS_ADIABATIC_MHD;
+    const bool fp32 = sc->prec == MHD_PREC_FP32_BULK;
+    const size_t rfield = (size_t)n * (fp32 ? sizeof(float) : sizeof(double));
     Layout L;
-    L.reg = align256(field * nv);
+    L.reg = is_mhd ? align256(register_bytes(n, fp32)) : align256(field * nv);
     L.nreg = is_mhd ? 3 : 2;
     L.W = is_mhd ? 0 : align256(field * nv);
-    L.F = align256(field * (is_mhd ? 21 : 3 * nv));
-    L.Rc = is_mhd ? align256(field * 3) : 0;
+    // for the FP32-bulk form the flux area also stages a canonical FP64 state (8 fields)
+    L.F = is_mhd ? align256(rfield * 21 > field * 8 ? rfield * 21 : field * 8) : align256(field * 3 * nv);
+    L.Rc = is_mhd ? align256(rfield * 3) : 0;
     size_t nb = blocks_for(n);
     const size_t nf = fused_grid(make_geo(g), choose_kz(g)).nblk;
     if (nf > nb) nb = nf;
@@ -170,29 +175,47 @@ struct Tick {
     }
 };
 
-// Compute the CFL step of the current state into scalars[0].
-mhd_status refresh_cfl(mhd_ctx* c)
+// The current state as canonical FP64 fields on the device: the register itself for the
+// FP64 form, else unpacked into the staging area.
+const double* canonical_view(mhd_ctx* c, hipError_t* e)
 {
-    const double* U = c->reg[c->cur];
+    *e = hipSuccess;
+    if (!c->fp32) return (const double*)c->reg[c->cur];
+    *e = launch_unpack_fp32(c->geo, c->reg[c->cur], (double*)c->F, c->stream);
+    return (const double*)c->F;
+}
+
+// Compute the CFL step of a canonical FP64 state into scalars[0].
+mhd_status cfl_of(mhd_ctx* c, const double* U)
+{
     Tick t(c, T_CFL);
     if (c->is_mhd) return dev(launch_cfl_mhd(c->geo, c->mp, U, c->partial, c->scalars, c->cfl_scale, c->stream));
     return dev(launch_cfl_dust(c->geo, c->dp, U, c->partial, c->scalars, c->cfl_scale, c->stream));
 }
 
+mhd_status refresh_cfl(mhd_ctx* c)
+{
+    hipError_t e;
+    const double* U = canonical_view(c, &e);
+    if (e != hipSuccess) return MHD_E_DEVICE;
+    return cfl_of(c, U);
+}
+
 // One stage: fluxes of `in`, then out = g0 in + g1 base + bdt L(in) (and, if last,
 // the CFL step of out into scalars[0]).
-mhd_status mhd_stage(mhd_ctx* c, int recon, const double* in, const double* base, double* out,
-                     StageCoef co, bool corrector, bool last)
+mhd_status mhd_stage(mhd_ctx* c, int recon, void* in, void* base, void* out, StageCoef co,
+                     bool corrector, bool last)
 {
     hipError_t e;
     {
         Tick t(c, corrector ? T_MHD_FLUX_CORR : T_MHD_FLUX_PRED);
-        e = launch_mhd_flux3(c->geo, c->mp, c->fg, recon, c->scheme.riemann, in, c->F, c->Rc, c->stream);
+        e = launch_mhd_flux3(c->geo, c->mp, c->fg, c->fp32, recon, c->scheme.riemann, in, c->F, c->Rc,
+                             c->stream);
     }
     if (e == hipSuccess) {
         Tick t(c, corrector ? T_MHD_CT_CORR : T_MHD_CT_PRED);
-        e = launch_mhd_ct_update(c->geo, c->mp, c->fg, in, base, c->F, c->Rc, out, co, c->partial,
-                                 last ? c->scalars : nullptr, c->cfl_scale, c->stream);
+        e = launch_mhd_ct_update(c->geo, c->mp, c->fg, c->fp32, in, base, c->F, c->Rc, out, co,
+                                 c->partial, last ? c->scalars : nullptr, c->cfl_scale, c->stream);
     }
     return dev(e);
 }
@@ -201,9 +224,9 @@ mhd_status mhd_stage(mhd_ctx* c, int recon, const double* in, const double* base
 mhd_status step_mhd(mhd_ctx* c, double dt)
 {
     const int s0 = c->cur, s1 = (c->cur + 1) % 3, s2 = (c->cur + 2) % 3;
-    double* S = c->reg[s0];
-    double* A = c->reg[s1];
-    double* B = c->reg[s2];
+    void* S = c->reg[s0];
+    void* A = c->reg[s1];
+    void* B = c->reg[s2];
     mhd_status st;
     switch (c->scheme.integ) {
     case MHD_INT_VL2:
@@ -229,8 +252,8 @@ mhd_status step_mhd(mhd_ctx* c, double dt)
 
 mhd_status step_dust(mhd_ctx* c, double dt)
 {
-    double* u = c->reg[c->cur];
-    double* U1 = c->reg[1 - c->cur];
+    double* u = (double*)c->reg[c->cur];
+    double* U1 = (double*)c->reg[1 - c->cur];
     const int recon = c->scheme.recon;
     hipError_t e = hipSuccess;
     for (int stage = 0; stage < 2 && e == hipSuccess; ++stage) {
@@ -241,15 +264,15 @@ mhd_status step_dust(mhd_ctx* c, double dt)
         }
         if (e == hipSuccess) {
             Tick t(c, T_DUST_FLUX);
-            e = launch_dust_fluxes(c->geo, c->dp, recon, c->W, c->F, c->stream);
+            e = launch_dust_fluxes(c->geo, c->dp, recon, c->W, (double*)c->F, c->stream);
         }
         if (e != hipSuccess) break;
         if (stage == 0) {
             Tick t(c, T_IMEX_STAGE1);
-            e = launch_imex_stage1(c->geo, c->dp, u, c->F, U1, dt, c->stream);
+            e = launch_imex_stage1(c->geo, c->dp, u, (const double*)c->F, U1, dt, c->stream);
         } else {
             Tick t(c, T_IMEX_STAGE2);
-            e = launch_imex_stage2(c->geo, c->dp, u, U1, c->F, dt, c->stream);
+            e = launch_imex_stage2(c->geo, c->dp, u, U1, (const double*)c->F, dt, c->stream);
         }
     }
     return dev(e);
@@ -278,7 +301,7 @@ mhd_status mhd_workspace_bytes(const mhd_grid* grid, const mhd_physics* phys,
     if (!bytes) return MHD_E_INVAL;
     mhd_status st = validate(grid, phys, scheme);
     if (st != MHD_OK) return st;
-    *bytes = layout(grid, phys).total;
+    *bytes = layout(grid, phys, scheme).total;
     return MHD_OK;
 }
 
@@ -290,7 +313,7 @@ mhd_status mhd_create(const mhd_grid* grid, const mhd_physics* phys, const mhd_s
     mhd_status st = validate(grid, phys, scheme);
     if (st != MHD_OK) return st;
     if (!device_workspace || ((uintptr_t)device_workspace & 255u)) return MHD_E_INVAL;
-    const Layout L = layout(grid, phys);
+    const Layout L = layout(grid, phys, scheme);
     if (bytes < L.total) return MHD_E_NOMEM;
 
     mhd_ctx* c = new (std::nothrow) mhd_ctx;
@@ -310,7 +333,9 @@ mhd_status mhd_create(const mhd_grid* grid, const mhd_physics* phys, const mhd_s
     c->mp.gm1inv = 1.0 / (phys->gamma - 1.0);
     c->mp.rho_floor = phys->rho_floor;
     c->mp.p_floor = phys->p_floor;
-    c->mp.hlld_eps = scheme->hlld_eps;
+    c->fp32 = scheme->prec == MHD_PREC_FP32_BULK;
+    // below single-precision round-off the HLLD degeneracy test would never fire
+    c->mp.hlld_eps = c->fp32 && scheme->hlld_eps < 1e-6 ? 1e-6 : scheme->hlld_eps;
     c->dp.nd = phys->ndust;
     c->dp.cs = phys->cs_iso;
     c->dp.rho_floor = phys->rho_floor;
@@ -325,12 +350,12 @@ mhd_status mhd_create(const mhd_grid* grid, const mhd_physics* phys, const mhd_s
 
     char* base = (char*)device_workspace;
     for (size_t r = 0; r < 3; ++r) {
-        c->reg[r] = r < L.nreg ? (double*)base : nullptr;
+        c->reg[r] = r < L.nreg ? (void*)base : nullptr;
         if (r < L.nreg) base += L.reg;
     }
     c->W = L.W ? (double*)base : nullptr; base += L.W;
-    c->F = (double*)base; base += L.F;
-    c->Rc = L.Rc ? (double*)base : nullptr; base += L.Rc;
+    c->F = (void*)base; base += L.F;
+    c->Rc = L.Rc ? (void*)base : nullptr; base += L.Rc;
     c->partial = (double*)base; base += L.partial;
     c->scalars = (double*)base;
     c->cur = 0;
@@ -349,24 +374,39 @@ mhd_status mhd_set_state(mhd_ctx* c, const double* src, int src_is_device)
 {
     if (!c || !src) return MHD_E_INVAL;
     const size_t bytes = (size_t)c->n * c->nvar * sizeof(double);
-    hipError_t e = hipMemcpyAsync(c->reg[c->cur], src, bytes,
-                                  src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                                  c->stream);
-    if (e != hipSuccess) return MHD_E_DEVICE;
-    if (!src_is_device) {
-        e = hipStreamSynchronize(c->stream);
-        if (e != hipSuccess) return MHD_E_DEVICE;
+    hipError_t e = hipSuccess;
+    // the canonical FP64 source on the device: the register (FP64 form) or the staging
+    // area (FP32-bulk form, or a host source that must be copied first)
+    const double* canon = src;
+    if (!c->fp32) {
+        e = hipMemcpyAsync(c->reg[c->cur], src, bytes,
+                           src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream);
+        canon = (const double*)c->reg[c->cur];
+    } else if (!src_is_device) {
+        e = hipMemcpyAsync(c->F, src, bytes, hipMemcpyHostToDevice, c->stream);
+        canon = (const double*)c->F;
     }
-    return refresh_cfl(c);
+    if (e == hipSuccess && !src_is_device) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return MHD_E_DEVICE;
+    // the time step of the state as given, then (FP32-bulk) its packed register
+    mhd_status st = cfl_of(c, canon);
+    if (st != MHD_OK || !c->fp32) return st;
+    return dev(launch_pack_fp32(c->geo, canon, c->reg[c->cur], c->stream));
 }
 
 mhd_status mhd_get_state(mhd_ctx* c, double* dst, int dst_is_device)
 {
     if (!c || !dst) return MHD_E_INVAL;
     const size_t bytes = (size_t)c->n * c->nvar * sizeof(double);
-    hipError_t e = hipMemcpyAsync(dst, c->reg[c->cur], bytes,
-                                  dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                                  c->stream);
+    hipError_t e;
+    if (c->fp32 && dst_is_device) {
+        e = launch_unpack_fp32(c->geo, c->reg[c->cur], dst, c->stream);
+        return dev(e);
+    }
+    const double* canon = canonical_view(c, &e);
+    if (e != hipSuccess) return MHD_E_DEVICE;
+    e = hipMemcpyAsync(dst, canon, bytes, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                       c->stream);
     if (e != hipSuccess) return MHD_E_DEVICE;
     if (!dst_is_device) return dev(hipStreamSynchronize(c->stream));
     return MHD_OK;
@@ -399,8 +439,11 @@ mhd_status mhd_diagnostics(mhd_ctx* c, double* out, int n)
     if (!c || !out) return MHD_E_INVAL;
     const int nq = diag_count(c->phys.ndust);
     if (n < nq) return MHD_E_INVAL;
-    hipError_t e = launch_diag(c->geo, c->is_mhd ? 1 : 0, c->is_mhd ? 0 : c->phys.ndust,
-                               c->reg[c->cur], c->partial, c->scalars + 1, c->stream);
+    hipError_t e;
+    const double* canon = canonical_view(c, &e);
+    if (e == hipSuccess)
+        e = launch_diag(c->geo, c->is_mhd ? 1 : 0, c->is_mhd ? 0 : c->phys.ndust, canon, c->partial,
+                        c->scalars + 1, c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(out, c->scalars + 1, sizeof(double) * nq, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

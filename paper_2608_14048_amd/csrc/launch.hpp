@@ -27,17 +27,54 @@ struct FusedGrid {
     unsigned int nty2, nblk2;     // tiles along y and workgroups of the CT/update kernel
 };
 FusedGrid fused_grid(const Geo& g, int kz);
-// U: 8 fields (rho, M1..3, E, b1..3) of the stage input.
-// F: 7 fields per direction, dir-major (mass, Mx, My, Mz, energy, E_t1, E_t2); Rc: 3
-// fields of the cell E = -v x B.
-hipError_t launch_mhd_flux3(const Geo& g, const MhdParams& p, const FusedGrid& fg, int recon,
-                            int riemann, const double* U, double* F, double* Rc, hipStream_t s);
+
+// A state register of the MHD path by role.  FP64 form (R = double): the 8 canonical
+// fields rho, M1..3, E, b1..3.  FP32-bulk form (R = float): E (double) first, then
+// rho, M1..3, b1..3 as float.
+template <class R>
+struct RegView {
+    R* rho;
+    R* m[3];
+    R* b[3];
+    double* E;
+};
+template <class R>
+inline RegView<R> reg_view(void* base, long long n)
+{
+    RegView<R> v;
+    if constexpr (sizeof(R) == sizeof(double)) {
+        R* f = (R*)base;
+        v.rho = f;
+        for (int a = 0; a < 3; ++a) v.m[a] = f + (1 + a) * n;
+        v.E = (double*)(f + 4 * n);
+        for (int a = 0; a < 3; ++a) v.b[a] = f + (5 + a) * n;
+    } else {
+        v.E = (double*)base;
+        R* f = (R*)(v.E + n);
+        v.rho = f;
+        for (int a = 0; a < 3; ++a) v.m[a] = f + (1 + a) * n;
+        for (int a = 0; a < 3; ++a) v.b[a] = f + (4 + a) * n;
+    }
+    return v;
+}
+inline size_t register_bytes(long long n, bool fp32)
+{
+    return fp32 ? (size_t)n * (sizeof(double) + 7 * sizeof(float)) : (size_t)n * 8 * sizeof(double);
+}
+
+// U: the stage-input register.  F: 7 fields per direction, dir-major (mass, Mx, My, Mz,
+// energy, E_t1, E_t2); Rc: 3 fields of the cell E = -v x B (both in the path's real).
+hipError_t launch_mhd_flux3(const Geo& g, const MhdParams& p, const FusedGrid& fg, bool fp32,
+                            int recon, int riemann, void* U, void* F, void* Rc, hipStream_t s);
 // out = g0 in + g1 base + bdt L; out must not alias in or base.  With dt_out the CFL
 // step of out (times cfl_scale) is reduced into dt_out via one partial per workgroup.
-hipError_t launch_mhd_ct_update(const Geo& g, const MhdParams& p, const FusedGrid& fg,
-                                const double* in, const double* base, const double* F,
-                                const double* Rc, double* out, StageCoef coef, double* partial,
-                                double* dt_out, double cfl_scale, hipStream_t s);
+hipError_t launch_mhd_ct_update(const Geo& g, const MhdParams& p, const FusedGrid& fg, bool fp32,
+                                void* in, void* base, const void* F, const void* Rc, void* out,
+                                StageCoef coef, double* partial, double* dt_out, double cfl_scale,
+                                hipStream_t s);
+// FP32-bulk register <-> canonical FP64 state (8 fields).
+hipError_t launch_pack_fp32(const Geo& g, const double* canon, void* reg, hipStream_t s);
+hipError_t launch_unpack_fp32(const Geo& g, const void* reg, double* canon, hipStream_t s);
 
 // ---- CFL and diagnostics ----
 // partial: ceil(n/kBlock) doubles; dt_out: 1 double on the device.

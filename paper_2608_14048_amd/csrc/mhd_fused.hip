@@ -18,8 +18,14 @@
 //   the CFL minimum of eq. (cfl) is taken over the updated state in the same pass
 //   (the updated right-hand faces needed for B_cc come from the same edge values).
 //
-// Layout: everything is [field][nz][ny][nx] FP64, x fastest; lanes of a wavefront run
-// along x so every global access is a contiguous 512-byte row segment.
+// Precision: templated on the real type R.  R = double is the FP64 path.  R = float is
+// the FP32-bulk form: density, momenta, face fields, reconstruction, Riemann solves, CT
+// and the updates in FP32, while the total energy is stored in FP64 and both the
+// pressure recovery p = (gamma-1)(E - kinetic - magnetic) and the energy update (from
+// the FP32 fluxes) are done in FP64.
+//
+// Layout: every field is [nz][ny][nx], x fastest; lanes of a wavefront run along x so
+// every global access is a contiguous row segment.
 #include "launch.hpp"
 #include "physics.hpp"
 
@@ -69,72 +75,74 @@ struct Stencil<2> {
     static constexpr int L = 3, R = 2;
 };
 
-// Uniform base pointers of the 8 fields of a state register.
-struct Fields8 {
-    const double* f[8];
-};
-__device__ __forceinline__ Fields8 fields8(const double* U, long long n)
+template <class T>
+__device__ __forceinline__ T ldT(const T* __restrict__ base, unsigned int idx)
 {
-    Fields8 r;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) r.f[q] = U + q * n;
-    return r;
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (unsigned int)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void stT(T* base, unsigned int idx, T v)
+{
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (unsigned int)sizeof(T)) = v;
 }
 
 // Primitives of cell (x, y, z) of the stage input (all indices already periodic).
+template <class R>
 struct Prim8 {
-    double d, vx, vy, vz, p, bx, by, bz;
+    R d, vx, vy, vz, p, bx, by, bz;
 };
 
-__device__ __forceinline__ Prim8 load_prims(const Geo& g, const MhdParams& P, const Fields8& U,
-                                            int x, int y, int z)
+template <class R>
+__device__ __forceinline__ Prim8<R> load_prims(const Geo& g, const MhdParams& P, const RegView<R>& U,
+                                               int x, int y, int z)
 {
     const unsigned int c = ((unsigned int)z * (unsigned int)g.ny + (unsigned int)y) * (unsigned int)g.nx + x;
-    const unsigned int o = c * 8u;
-    const unsigned int ox = (x + 1 == g.nx ? c - x : c + 1) * 8u;
-    const unsigned int oy = (y + 1 == g.ny ? c - (unsigned int)y * g.nx : c + g.nx) * 8u;
-    const unsigned int oz = (z + 1 == g.nz ? c - (unsigned int)z * g.nx * g.ny : c + (unsigned int)g.nx * g.ny) * 8u;
-    Prim8 w;
-    w.bx = 0.5 * (ld_at(U.f[5], o) + ld_at(U.f[5], ox));
-    w.by = 0.5 * (ld_at(U.f[6], o) + ld_at(U.f[6], oy));
-    w.bz = 0.5 * (ld_at(U.f[7], o) + ld_at(U.f[7], oz));
-    double d = ld_at(U.f[0], o);
-    if (d < P.rho_floor) d = P.rho_floor;
+    const unsigned int cx = x + 1 == g.nx ? c - x : c + 1;
+    const unsigned int cy = y + 1 == g.ny ? c - (unsigned int)y * g.nx : c + g.nx;
+    const unsigned int cz = z + 1 == g.nz ? c - (unsigned int)z * g.nx * g.ny : c + (unsigned int)g.nx * g.ny;
+    Prim8<R> w;
+    w.bx = R(0.5) * (ldT(U.b[0], c) + ldT(U.b[0], cx));
+    w.by = R(0.5) * (ldT(U.b[1], c) + ldT(U.b[1], cy));
+    w.bz = R(0.5) * (ldT(U.b[2], c) + ldT(U.b[2], cz));
+    R d = ldT(U.rho, c);
+    if (d < R(P.rho_floor)) d = R(P.rho_floor);
     w.d = d;
-    const double id = 1.0 / d;
-    w.vx = ld_at(U.f[1], o) * id;
-    w.vy = ld_at(U.f[2], o) * id;
-    w.vz = ld_at(U.f[3], o) * id;
-    const double ke = 0.5 * d * ((w.vx * w.vx + w.vy * w.vy) + w.vz * w.vz);
-    const double me = 0.5 * ((w.bx * w.bx + w.by * w.by) + w.bz * w.bz);
-    double pr = (P.gamma - 1.0) * ((ld_at(U.f[4], o) - ke) - me);
+    const R id = rcp(d);
+    w.vx = ldT(U.m[0], c) * id;
+    w.vy = ldT(U.m[1], c) * id;
+    w.vz = ldT(U.m[2], c) * id;
+    // pressure from the total energy in FP64
+    const double dd = d, vx = w.vx, vy = w.vy, vz = w.vz, bx = w.bx, by = w.by, bz = w.bz;
+    const double ke = 0.5 * dd * ((vx * vx + vy * vy) + vz * vz);
+    const double me = 0.5 * ((bx * bx + by * by) + bz * bz);
+    double pr = (P.gamma - 1.0) * ((ldT(U.E, c) - ke) - me);
     if (pr < P.p_floor) pr = P.p_floor;
-    w.p = pr;
+    w.p = R(pr);
     return w;
 }
 
-template <int RS>
-__device__ __forceinline__ void solve(const Prim7& L, const Prim7& R, double bn, const MhdParams& P,
-                                      Flux7& f)
+template <int RS, class R>
+__device__ __forceinline__ void solve(const Prim7<R>& L, const Prim7<R>& Rt, R bn, const MhdParams& P,
+                                      Flux7<R>& f)
 {
     if (RS == 1)
-        riemann_hlld(L, R, bn, P.gamma, P.gm1inv, P.hlld_eps, f);
+        riemann_hlld(L, Rt, bn, R(P.gamma), R(P.gm1inv), R(P.hlld_eps), f);
     else
-        riemann_hlle(L, R, bn, P.gamma, P.gm1inv, f);
+        riemann_hlle(L, Rt, bn, R(P.gamma), R(P.gm1inv), f);
 }
 
 // Reconstruction along z as a pipeline over the planes a column visits: each new plane
 // costs one slope, one interface and one limiter (PPM), one slope (PLM) or nothing (DC);
 // push() returns the two states on the face k - 1/2 when plane k + AHEAD arrives.
-template <int RECON>
+template <int RECON, class R>
 struct ZPipe;
 
-template <>
-struct ZPipe<0> {
-    static constexpr int AHEAD = 0, PRIME = 1;  // planes k0-1 .. k0-1 before the march
-    double prev;
-    __device__ void prime(const double* a) { prev = a[0]; }
-    __device__ void push(double a, double& aL, double& aR)
+template <class R>
+struct ZPipe<0, R> {
+    static constexpr int AHEAD = 0, PRIME = 1;  // plane k0-1 before the march
+    R prev;
+    __device__ void prime(const R* a) { prev = a[0]; }
+    __device__ void push(R a, R& aL, R& aR)
     {
         aL = prev;
         aR = a;
@@ -142,52 +150,52 @@ struct ZPipe<0> {
     }
 };
 
-template <>
-struct ZPipe<1> {
+template <class R>
+struct ZPipe<1, R> {
     static constexpr int AHEAD = 1, PRIME = 3;  // planes k0-2 .. k0
-    double am, a0, apl;  // a(k-1), a(k), a_+(k-1)
-    __device__ void prime(const double* a)
+    R am, a0, apl;  // a(k-1), a(k), a_+(k-1)
+    __device__ void prime(const R* a)
     {
-        apl = a[1] + 0.5 * slope_vl(a[0], a[1], a[2]);
+        apl = a[1] + R(0.5) * slope_vl(a[0], a[1], a[2]);
         am = a[1];
         a0 = a[2];
     }
-    __device__ void push(double a, double& aL, double& aR)
+    __device__ void push(R a, R& aL, R& aR)
     {
-        const double d = slope_vl(am, a0, a);
+        const R d = slope_vl(am, a0, a);
         aL = apl;
-        aR = a0 - 0.5 * d;
-        apl = a0 + 0.5 * d;
+        aR = a0 - R(0.5) * d;
+        apl = a0 + R(0.5) * d;
         am = a0;
         a0 = a;
     }
 };
 
-template <>
-struct ZPipe<2> {
+template <class R>
+struct ZPipe<2, R> {
     static constexpr int AHEAD = 2, PRIME = 5;  // planes k0-3 .. k0+1
-    double a0, a1, m0, ilo, apl;  // a(k), a(k+1), slope(k), a_{k-1/2}, a_+(k-1)
-    __device__ void prime(const double* a)
+    R a0, a1, m0, ilo, apl;  // a(k), a(k+1), slope(k), a_{k-1/2}, a_+(k-1)
+    __device__ void prime(const R* a)
     {
-        const double s1 = cw_slope(a[0], a[1], a[2]);
-        const double s2 = cw_slope(a[1], a[2], a[3]);
-        const double s3 = cw_slope(a[2], a[3], a[4]);
-        double lo = cw_interface(a[1], a[2], s1, s2);  // a_{k0-3/2}
-        double hi = cw_interface(a[2], a[3], s2, s3);  // a_{k0-1/2}
+        const R s1 = cw_slope(a[0], a[1], a[2]);
+        const R s2 = cw_slope(a[1], a[2], a[3]);
+        const R s3 = cw_slope(a[2], a[3], a[4]);
+        R lo = cw_interface(a[1], a[2], s1, s2);  // a_{k0-3/2}
+        R hi = cw_interface(a[2], a[3], s2, s3);  // a_{k0-1/2}
         ilo = hi;
-        cw_limit(a[2], lo, hi);                        // cell k0-1
+        cw_limit(a[2], lo, hi);                   // cell k0-1
         apl = hi;
         a0 = a[3];
         a1 = a[4];
         m0 = s3;
     }
-    __device__ void push(double a, double& aL, double& aR)
+    __device__ void push(R a, R& aL, R& aR)
     {
-        const double m1 = cw_slope(a0, a1, a);         // slope of cell k+1
-        double lo = ilo;
-        double hi = cw_interface(a0, a1, m0, m1);      // a_{k+1/2}
+        const R m1 = cw_slope(a0, a1, a);         // slope of cell k+1
+        R lo = ilo;
+        R hi = cw_interface(a0, a1, m0, m1);      // a_{k+1/2}
         ilo = hi;
-        cw_limit(a0, lo, hi);                          // cell k
+        cw_limit(a0, lo, hi);                     // cell k
         aL = apl;
         aR = lo;
         apl = hi;
@@ -203,16 +211,15 @@ struct ZPipe<2> {
 // K1: face fluxes of all three directions
 // ----------------------------------------------------------------------------------
 
-template <int RECON, int RS>
-__global__ __launch_bounds__(TX* TY) void k_flux3(Geo g, MhdParams P, const double* __restrict__ Ub,
-                                                 double* __restrict__ F, double* __restrict__ Rc,
-                                                 int kz, unsigned int ntx, unsigned int nty,
-                                                 unsigned int nblk)
+template <int RECON, int RS, class R>
+__global__ __launch_bounds__(TX* TY) void k_flux3(Geo g, MhdParams P, RegView<R> U, R* __restrict__ F,
+                                                 R* __restrict__ Rc, int kz, unsigned int ntx,
+                                                 unsigned int nty, unsigned int nblk)
 {
     constexpr int SL = Stencil<RECON>::L, SR = Stencil<RECON>::R;
     constexpr int LX = TX + SL + SR, LY = TY + SL + SR;
-    using Pipe = ZPipe<RECON>;
-    __shared__ double sw[8][LY][LX];
+    using Pipe = ZPipe<RECON, R>;
+    __shared__ R sw[8][LY][LX];
 
     const unsigned int t = xcd_tile(blockIdx.x, nblk);
     const int x0 = (int)(t % ntx) * TX;
@@ -225,18 +232,17 @@ __global__ __launch_bounds__(TX* TY) void k_flux3(Geo g, MhdParams P, const doub
     const int ic = live ? i : 0, jc = live ? j : 0;
     const long long n = g.n;
     const unsigned int plane = (unsigned int)g.nx * (unsigned int)g.ny;
-    const Fields8 U = fields8(Ub, n);
-    double* Fo[21];
+    R* Fo[21];
 #pragma unroll
     for (int q = 0; q < 21; ++q) Fo[q] = F + q * n;
 
     // z pipeline of the face-frame variables (rho, v_z, v_x, v_y, p, B_x, B_y)
     Pipe zp[7];
     {
-        double pre[7][Pipe::PRIME];
+        R pre[7][Pipe::PRIME];
 #pragma unroll
         for (int s = 0; s < Pipe::PRIME; ++s) {
-            const Prim8 w = load_prims(g, P, U, ic, jc, wrap_any(k0 - Pipe::PRIME + Pipe::AHEAD + s, g.nz));
+            const Prim8<R> w = load_prims(g, P, U, ic, jc, wrap_any(k0 - Pipe::PRIME + Pipe::AHEAD + s, g.nz));
             pre[0][s] = w.d; pre[1][s] = w.vz; pre[2][s] = w.vx; pre[3][s] = w.vy;
             pre[4][s] = w.p; pre[5][s] = w.bx; pre[6][s] = w.by;
         }
@@ -251,70 +257,68 @@ __global__ __launch_bounds__(TX* TY) void k_flux3(Geo g, MhdParams P, const doub
             const bool xh = cc < SL || cc >= SL + TX, yh = r < SL || r >= SL + TY;
             if (xh && yh) continue;
             const int gx = wrap_any(x0 + cc - SL, g.nx), gy = wrap_any(y0 + r - SL, g.ny);
-            const Prim8 w = load_prims(g, P, U, gx, gy, k);
+            const Prim8<R> w = load_prims(g, P, U, gx, gy, k);
             sw[0][r][cc] = w.d; sw[1][r][cc] = w.vx; sw[2][r][cc] = w.vy; sw[3][r][cc] = w.vz;
             sw[4][r][cc] = w.p; sw[5][r][cc] = w.bx; sw[6][r][cc] = w.by; sw[7][r][cc] = w.bz;
         }
         // newest plane of the z pipeline
-        const Prim8 wz = load_prims(g, P, U, ic, jc, wrap_any(k + Pipe::AHEAD, g.nz));
+        const Prim8<R> wz = load_prims(g, P, U, ic, jc, wrap_any(k + Pipe::AHEAD, g.nz));
         __syncthreads();
 
-        const unsigned int o = ((unsigned int)k * plane + (unsigned int)jc * g.nx + ic) * 8u;
-        double st[6];
-        Prim7 L, R;
-        Flux7 f;
+        const unsigned int c = (unsigned int)k * plane + (unsigned int)jc * g.nx + ic;
+        R st[6];
+        Prim7<R> L, Rt;
+        Flux7<R> f;
         // ---- z faces from the pipeline: (rho, vz, vx, vy, p, Bx, By)
-        zp[0].push(wz.d, L.d, R.d);
-        zp[1].push(wz.vz, L.vn, R.vn);
-        zp[2].push(wz.vx, L.vt1, R.vt1);
-        zp[3].push(wz.vy, L.vt2, R.vt2);
-        zp[4].push(wz.p, L.p, R.p);
-        zp[5].push(wz.bx, L.bt1, R.bt1);
-        zp[6].push(wz.by, L.bt2, R.bt2);
+        zp[0].push(wz.d, L.d, Rt.d);
+        zp[1].push(wz.vz, L.vn, Rt.vn);
+        zp[2].push(wz.vx, L.vt1, Rt.vt1);
+        zp[3].push(wz.vy, L.vt2, Rt.vt2);
+        zp[4].push(wz.p, L.p, Rt.p);
+        zp[5].push(wz.bx, L.bt1, Rt.bt1);
+        zp[6].push(wz.by, L.bt2, Rt.bt2);
         if (live) {
-            solve<RS>(L, R, ld_at(U.f[7], o), P, f);
-            st_at(Fo[14], o, f.d); st_at(Fo[17], o, f.mn); st_at(Fo[15], o, f.mt1); st_at(Fo[16], o, f.mt2);
-            st_at(Fo[18], o, f.e); st_at(Fo[19], o, f.bt2); st_at(Fo[20], o, -f.bt1);
-        }
-        if (live) {
+            solve<RS>(L, Rt, ldT(U.b[2], c), P, f);
+            stT(Fo[14], c, f.d); stT(Fo[17], c, f.mn); stT(Fo[15], c, f.mt1); stT(Fo[16], c, f.mt2);
+            stT(Fo[18], c, f.e); stT(Fo[19], c, f.bt2); stT(Fo[20], c, -f.bt1);
             // ---- x faces: (rho, vx, vy, vz, p, By, Bz)
             {
                 const int comp[7] = {0, 1, 2, 3, 4, 6, 7};
-                double* lr[7][2] = {{&L.d, &R.d}, {&L.vn, &R.vn}, {&L.vt1, &R.vt1}, {&L.vt2, &R.vt2},
-                                    {&L.p, &R.p}, {&L.bt1, &R.bt1}, {&L.bt2, &R.bt2}};
+                R* lr[7][2] = {{&L.d, &Rt.d}, {&L.vn, &Rt.vn}, {&L.vt1, &Rt.vt1}, {&L.vt2, &Rt.vt2},
+                               {&L.p, &Rt.p}, {&L.bt1, &Rt.bt1}, {&L.bt2, &Rt.bt2}};
 #pragma unroll
                 for (int v = 0; v < 7; ++v) {
 #pragma unroll
                     for (int s = -SL; s <= SR; ++s) st[3 + s] = sw[comp[v]][row + SL][lane + SL + s];
                     face_states<RECON>(st, *lr[v][0], *lr[v][1]);
                 }
-                solve<RS>(L, R, ld_at(U.f[5], o), P, f);
-                st_at(Fo[0], o, f.d); st_at(Fo[1], o, f.mn); st_at(Fo[2], o, f.mt1); st_at(Fo[3], o, f.mt2);
-                st_at(Fo[4], o, f.e); st_at(Fo[5], o, f.bt2); st_at(Fo[6], o, -f.bt1);
+                solve<RS>(L, Rt, ldT(U.b[0], c), P, f);
+                stT(Fo[0], c, f.d); stT(Fo[1], c, f.mn); stT(Fo[2], c, f.mt1); stT(Fo[3], c, f.mt2);
+                stT(Fo[4], c, f.e); stT(Fo[5], c, f.bt2); stT(Fo[6], c, -f.bt1);
             }
             // ---- y faces: (rho, vy, vz, vx, p, Bz, Bx)
             {
                 const int comp[7] = {0, 2, 3, 1, 4, 7, 5};
-                double* lr[7][2] = {{&L.d, &R.d}, {&L.vn, &R.vn}, {&L.vt1, &R.vt1}, {&L.vt2, &R.vt2},
-                                    {&L.p, &R.p}, {&L.bt1, &R.bt1}, {&L.bt2, &R.bt2}};
+                R* lr[7][2] = {{&L.d, &Rt.d}, {&L.vn, &Rt.vn}, {&L.vt1, &Rt.vt1}, {&L.vt2, &Rt.vt2},
+                               {&L.p, &Rt.p}, {&L.bt1, &Rt.bt1}, {&L.bt2, &Rt.bt2}};
 #pragma unroll
                 for (int v = 0; v < 7; ++v) {
 #pragma unroll
                     for (int s = -SL; s <= SR; ++s) st[3 + s] = sw[comp[v]][row + SL + s][lane + SL];
                     face_states<RECON>(st, *lr[v][0], *lr[v][1]);
                 }
-                solve<RS>(L, R, ld_at(U.f[6], o), P, f);
-                st_at(Fo[7], o, f.d); st_at(Fo[9], o, f.mn); st_at(Fo[10], o, f.mt1); st_at(Fo[8], o, f.mt2);
-                st_at(Fo[11], o, f.e); st_at(Fo[12], o, f.bt2); st_at(Fo[13], o, -f.bt1);
+                solve<RS>(L, Rt, ldT(U.b[1], c), P, f);
+                stT(Fo[7], c, f.d); stT(Fo[9], c, f.mn); stT(Fo[10], c, f.mt1); stT(Fo[8], c, f.mt2);
+                stT(Fo[11], c, f.e); stT(Fo[12], c, f.bt2); stT(Fo[13], c, -f.bt1);
             }
             // ---- cell field E = -v x B
             {
-                const double vx = sw[1][row + SL][lane + SL], vy = sw[2][row + SL][lane + SL];
-                const double vz = sw[3][row + SL][lane + SL], bx = sw[5][row + SL][lane + SL];
-                const double by = sw[6][row + SL][lane + SL], bz = sw[7][row + SL][lane + SL];
-                st_at(Rc, o, vz * by - vy * bz);
-                st_at(Rc + n, o, vx * bz - vz * bx);
-                st_at(Rc + 2 * n, o, vy * bx - vx * by);
+                const R vx = sw[1][row + SL][lane + SL], vy = sw[2][row + SL][lane + SL];
+                const R vz = sw[3][row + SL][lane + SL], bx = sw[5][row + SL][lane + SL];
+                const R by = sw[6][row + SL][lane + SL], bz = sw[7][row + SL][lane + SL];
+                stT(Rc, c, vz * by - vy * bz);
+                stT(Rc + n, c, vx * bz - vz * bx);
+                stT(Rc + 2 * n, c, vy * bx - vx * by);
             }
         }
         __syncthreads();
@@ -325,46 +329,48 @@ __global__ __launch_bounds__(TX* TY) void k_flux3(Geo g, MhdParams P, const doub
 // K2: edge EMFs, update, CFL
 // ----------------------------------------------------------------------------------
 
-__device__ __forceinline__ double gs_upwind(double m, double pos, double neg)
+template <class R>
+__device__ __forceinline__ R gs_upwind(R m, R pos, R neg)
 {
-    return m > 0.0 ? pos : (m < 0.0 ? neg : 0.5 * (pos + neg));
+    return m > R(0) ? pos : (m < R(0) ? neg : R(0.5) * (pos + neg));
 }
 
 // Gardiner-Stone edge value from the face values X (p-faces) and Y (q-faces), the cell
 // field R at the four cells around the edge and the mass fluxes through the faces.
-__device__ __forceinline__ double gs_edge(double X0, double Xm, double Y0, double Ym, double R00,
-                                          double Rm0, double R0m, double Rmm, double fp0, double fpm,
-                                          double fq0, double fqm)
+template <class R>
+__device__ __forceinline__ R gs_edge(R X0, R Xm, R Y0, R Ym, R R00, R Rm0, R R0m, R Rmm, R fp0, R fpm,
+                                     R fq0, R fqm)
 {
-    const double dqp = gs_upwind(fp0, Rm0 - Ym, R00 - Y0);
-    const double dqm = gs_upwind(fpm, Ym - Rmm, Y0 - R0m);
-    const double dpp = gs_upwind(fq0, R0m - Xm, R00 - X0);
-    const double dpm = gs_upwind(fqm, Xm - Rmm, X0 - Rm0);
-    return 0.25 * (((X0 + Xm) + (Y0 + Ym)) - ((dqp - dqm) + (dpp - dpm)));
+    const R dqp = gs_upwind(fp0, Rm0 - Ym, R00 - Y0);
+    const R dqm = gs_upwind(fpm, Ym - Rmm, Y0 - R0m);
+    const R dpp = gs_upwind(fq0, R0m - Xm, R00 - X0);
+    const R dpm = gs_upwind(fqm, Xm - Rmm, X0 - Rm0);
+    return R(0.25) * (((X0 + Xm) + (Y0 + Ym)) - ((dqp - dqm) + (dpp - dpm)));
 }
 
+template <class R>
 struct CtArgs {
-    const double* in;    // stage input register (8 fields)
-    const double* base;  // second register (8 fields); may equal in, never out
-    const double* F;     // 3 x 7 face fields
-    const double* Rc;    // 3 cell E fields
-    double* out;         // distinct from in and base
+    RegView<R> in;       // stage input register
+    RegView<R> base;     // second register; may equal in, never out
+    const R* F;          // 3 x 7 face fields
+    const R* Rc;         // 3 cell E fields
+    RegView<R> out;      // distinct from in and base
     double* partial;     // CFL partial minima, one per workgroup
     StageCoef co;
 };
 
 // CFL: reduce the time step of the output.  IN: the stage reads its input register
 // (g0 != 0 or a gas acceleration is set); otherwise only the base register is read.
-template <bool CFL, bool IN>
-__global__ __launch_bounds__(TX* TY2) void k_ct_update(Geo g, MhdParams P, CtArgs a, int kz,
-                                                     unsigned int ntx, unsigned int nty,
-                                                     unsigned int nblk)
+template <bool CFL, bool IN, class R>
+__global__ __launch_bounds__(TX* TY2) void k_ct_update(Geo g, MhdParams P, CtArgs<R> a, int kz,
+                                                      unsigned int ntx, unsigned int nty,
+                                                      unsigned int nblk)
 {
     // edges held for the tile: E_z on plane k, E_x / E_y on levels k-1/2 (slot lv^1)
     // and k+1/2 (slot lv); index ranges i in [0, TX], j in [0, TY2]
-    __shared__ double sEz[TY2 + 1][TX + 1];
-    __shared__ double sEx[2][TY2 + 1][TX + 1];
-    __shared__ double sEy[2][TY2 + 1][TX + 1];
+    __shared__ R sEz[TY2 + 1][TX + 1];
+    __shared__ R sEx[2][TY2 + 1][TX + 1];
+    __shared__ R sEy[2][TY2 + 1][TX + 1];
     __shared__ double sMin[TX * TY2 / 64];
 
     const unsigned int bt = xcd_tile(blockIdx.x, nblk);
@@ -377,46 +383,40 @@ __global__ __launch_bounds__(TX* TY2) void k_ct_update(Geo g, MhdParams P, CtArg
     const bool live = i < g.nx && j < g.ny;
     const long long n = g.n;
     const unsigned int nx = g.nx, plane = (unsigned int)g.nx * (unsigned int)g.ny;
-    // uniform bases: face fields (dir*7 + slot), cell E, registers
-    const double* Fb[21];
+    const R* Fb[21];
 #pragma unroll
     for (int q = 0; q < 21; ++q) Fb[q] = a.F + q * n;
-    const double* Rx = a.Rc;
-    const double* Ry = a.Rc + n;
-    const double* Rz = a.Rc + 2 * n;
-    const Fields8 In = fields8(a.in, n);
-    const Fields8 Bs = fields8(a.base, n);
-    double* Out[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) Out[q] = a.out + q * n;
+    const R* Rx = a.Rc;
+    const R* Ry = a.Rc + n;
+    const R* Rz = a.Rc + 2 * n;
 
-    auto off = [&](int x, int y, int z) -> unsigned int {
-        return ((unsigned int)z * plane + (unsigned int)y * nx + (unsigned int)x) * 8u;
+    auto at = [&](int x, int y, int z) -> unsigned int {
+        return (unsigned int)z * plane + (unsigned int)y * nx + (unsigned int)x;
     };
     // E_x at (x, y-1/2, z-1/2), E_y at (x-1/2, y, z-1/2), E_z at (x-1/2, y-1/2, z)
-    auto edge_x = [&](int x, int y, int z) -> double {
+    auto edge_x = [&](int x, int y, int z) -> R {
         const int ym = wrap_once(y - 1, g.ny), zm = wrap_once(z - 1, g.nz);
-        const unsigned int c = off(x, y, z), cy = off(x, ym, z), cz = off(x, y, zm), cyz = off(x, ym, zm);
+        const unsigned int c = at(x, y, z), cy = at(x, ym, z), cz = at(x, y, zm), cyz = at(x, ym, zm);
         // p = y, q = z: X on y-faces (slot 6 of the y sweep), Y on z-faces (slot 5 of z)
-        return gs_edge(ld_at(Fb[13], c), ld_at(Fb[13], cz), ld_at(Fb[19], c), ld_at(Fb[19], cy),
-                       ld_at(Rx, c), ld_at(Rx, cy), ld_at(Rx, cz), ld_at(Rx, cyz),
-                       ld_at(Fb[7], c), ld_at(Fb[7], cz), ld_at(Fb[14], c), ld_at(Fb[14], cy));
+        return gs_edge(ldT(Fb[13], c), ldT(Fb[13], cz), ldT(Fb[19], c), ldT(Fb[19], cy),
+                       ldT(Rx, c), ldT(Rx, cy), ldT(Rx, cz), ldT(Rx, cyz),
+                       ldT(Fb[7], c), ldT(Fb[7], cz), ldT(Fb[14], c), ldT(Fb[14], cy));
     };
-    auto edge_y = [&](int x, int y, int z) -> double {
+    auto edge_y = [&](int x, int y, int z) -> R {
         const int xm = wrap_once(x - 1, g.nx), zm = wrap_once(z - 1, g.nz);
-        const unsigned int c = off(x, y, z), cx = off(xm, y, z), cz = off(x, y, zm), cxz = off(xm, y, zm);
+        const unsigned int c = at(x, y, z), cx = at(xm, y, z), cz = at(x, y, zm), cxz = at(xm, y, zm);
         // p = z, q = x: X on z-faces (slot 6 of z), Y on x-faces (slot 5 of x)
-        return gs_edge(ld_at(Fb[20], c), ld_at(Fb[20], cx), ld_at(Fb[5], c), ld_at(Fb[5], cz),
-                       ld_at(Ry, c), ld_at(Ry, cz), ld_at(Ry, cx), ld_at(Ry, cxz),
-                       ld_at(Fb[14], c), ld_at(Fb[14], cx), ld_at(Fb[0], c), ld_at(Fb[0], cz));
+        return gs_edge(ldT(Fb[20], c), ldT(Fb[20], cx), ldT(Fb[5], c), ldT(Fb[5], cz),
+                       ldT(Ry, c), ldT(Ry, cz), ldT(Ry, cx), ldT(Ry, cxz),
+                       ldT(Fb[14], c), ldT(Fb[14], cx), ldT(Fb[0], c), ldT(Fb[0], cz));
     };
-    auto edge_z = [&](int x, int y, int z) -> double {
+    auto edge_z = [&](int x, int y, int z) -> R {
         const int xm = wrap_once(x - 1, g.nx), ym = wrap_once(y - 1, g.ny);
-        const unsigned int c = off(x, y, z), cx = off(xm, y, z), cy = off(x, ym, z), cxy = off(xm, ym, z);
+        const unsigned int c = at(x, y, z), cx = at(xm, y, z), cy = at(x, ym, z), cxy = at(xm, ym, z);
         // p = x, q = y: X on x-faces (slot 6 of x), Y on y-faces (slot 5 of y)
-        return gs_edge(ld_at(Fb[6], c), ld_at(Fb[6], cy), ld_at(Fb[12], c), ld_at(Fb[12], cx),
-                       ld_at(Rz, c), ld_at(Rz, cx), ld_at(Rz, cy), ld_at(Rz, cxy),
-                       ld_at(Fb[0], c), ld_at(Fb[0], cy), ld_at(Fb[7], c), ld_at(Fb[7], cx));
+        return gs_edge(ldT(Fb[6], c), ldT(Fb[6], cy), ldT(Fb[12], c), ldT(Fb[12], cx),
+                       ldT(Rz, c), ldT(Rz, cx), ldT(Rz, cy), ldT(Rz, cxy),
+                       ldT(Fb[0], c), ldT(Fb[0], cy), ldT(Fb[7], c), ldT(Fb[7], cx));
     };
     // level edges E_x, E_y at z-level zl - 1/2 for the tile (+1 ring on the high side)
     auto fill_level = [&](int slot, int zl) {
@@ -435,6 +435,8 @@ __global__ __launch_bounds__(TX* TY2) void k_ct_update(Geo g, MhdParams P, CtArg
     int lv = 0;
     fill_level(lv ^ 1, k0);  // level k0 - 1/2
     const double bdt = a.co.bdt, g0 = a.co.g0, g1 = a.co.g1;
+    const R bdtr = R(bdt), g0r = R(g0), g1r = R(g1);
+    const R idx = R(g.inv_dx[0]), idy = R(g.inv_dx[1]), idz = R(g.inv_dx[2]);
 
     for (int k = k0; k < k1; ++k) {
         // edges: E_z on plane k, E_x / E_y on level k + 1/2
@@ -451,64 +453,77 @@ __global__ __launch_bounds__(TX* TY2) void k_ct_update(Geo g, MhdParams P, CtArg
         if (live) {
             const int ip = i + 1 == g.nx ? 0 : i + 1, jp = j + 1 == g.ny ? 0 : j + 1;
             const int kp = k + 1 == g.nz ? 0 : k + 1;
-            const unsigned int c = off(i, j, k), cx = off(ip, j, k), cy = off(i, jp, k), cz = off(i, j, kp);
-            double L[5];
-            const int slot[5] = {0, 1, 2, 3, 4};
+            const unsigned int c = at(i, j, k), cx = at(ip, j, k), cy = at(i, jp, k), cz = at(i, j, kp);
+            // flux divergence: density and momenta in R, energy in FP64
+            R L[4];
 #pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                const double fx = (ld_at(Fb[slot[v]], cx) - ld_at(Fb[slot[v]], c)) * g.inv_dx[0];
-                const double fy = (ld_at(Fb[7 + slot[v]], cy) - ld_at(Fb[7 + slot[v]], c)) * g.inv_dx[1];
-                const double fz = (ld_at(Fb[14 + slot[v]], cz) - ld_at(Fb[14 + slot[v]], c)) * g.inv_dx[2];
+            for (int v = 0; v < 4; ++v) {
+                const R fx = (ldT(Fb[v], cx) - ldT(Fb[v], c)) * idx;
+                const R fy = (ldT(Fb[7 + v], cy) - ldT(Fb[7 + v], c)) * idy;
+                const R fz = (ldT(Fb[14 + v], cz) - ldT(Fb[14 + v], c)) * idz;
                 L[v] = -((fx + fy) + fz);
             }
-            double o[5];
+            double LE;
+            {
+                const double fx = ((double)ldT(Fb[4], cx) - (double)ldT(Fb[4], c)) * g.inv_dx[0];
+                const double fy = ((double)ldT(Fb[11], cy) - (double)ldT(Fb[11], c)) * g.inv_dx[1];
+                const double fz = ((double)ldT(Fb[18], cz) - (double)ldT(Fb[18], c)) * g.inv_dx[2];
+                LE = -((fx + fy) + fz);
+            }
+            R o[4];
+            double oE;
             if (IN) {
-                double in5[5];
+                const R rho_in = ldT(a.in.rho, c);
+                const R m_in[3] = {ldT(a.in.m[0], c), ldT(a.in.m[1], c), ldT(a.in.m[2], c)};
+                L[1] += rho_in * R(P.gacc[0]);
+                L[2] += rho_in * R(P.gacc[1]);
+                L[3] += rho_in * R(P.gacc[2]);
+                LE += ((double)m_in[0] * P.gacc[0] + (double)m_in[1] * P.gacc[1]) + (double)m_in[2] * P.gacc[2];
+                o[0] = (g0r * rho_in + g1r * ldT(a.base.rho, c)) + bdtr * L[0];
 #pragma unroll
-                for (int v = 0; v < 5; ++v) in5[v] = ld_at(In.f[v], c);
-                L[1] += in5[0] * P.gacc[0];
-                L[2] += in5[0] * P.gacc[1];
-                L[3] += in5[0] * P.gacc[2];
-                L[4] += (in5[1] * P.gacc[0] + in5[2] * P.gacc[1]) + in5[3] * P.gacc[2];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) o[v] = (g0 * in5[v] + g1 * ld_at(Bs.f[v], c)) + bdt * L[v];
+                for (int v = 0; v < 3; ++v) o[1 + v] = (g0r * m_in[v] + g1r * ldT(a.base.m[v], c)) + bdtr * L[1 + v];
+                oE = (g0 * ldT(a.in.E, c) + g1 * ldT(a.base.E, c)) + bdt * LE;
             } else {
+                o[0] = g1r * ldT(a.base.rho, c) + bdtr * L[0];
 #pragma unroll
-                for (int v = 0; v < 5; ++v) o[v] = g1 * ld_at(Bs.f[v], c) + bdt * L[v];
+                for (int v = 0; v < 3; ++v) o[1 + v] = g1r * ldT(a.base.m[v], c) + bdtr * L[1 + v];
+                oE = g1 * ldT(a.base.E, c) + bdt * LE;
             }
 
             // faces of this cell: b1 at x_{i-1/2}, b2 at y_{j-1/2}, b3 at z_{k-1/2}
             const int ol = lv ^ 1, nl = lv;
+            auto comb = [&](int comp, unsigned int cc, R lb) -> R {
+                return (IN ? g0r * ldT(a.in.b[comp], cc) + g1r * ldT(a.base.b[comp], cc)
+                           : g1r * ldT(a.base.b[comp], cc)) + bdtr * lb;
+            };
             auto nb1 = [&](int xl, unsigned int cc) {  // new B_x on the face at tile column xl
-                const double lb = -((sEz[row + 1][xl] - sEz[row][xl]) * g.inv_dx[1] -
-                                    (sEy[nl][row][xl] - sEy[ol][row][xl]) * g.inv_dx[2]);
-                return (IN ? g0 * ld_at(In.f[5], cc) + g1 * ld_at(Bs.f[5], cc) : g1 * ld_at(Bs.f[5], cc)) + bdt * lb;
+                const R lb = -((sEz[row + 1][xl] - sEz[row][xl]) * idy - (sEy[nl][row][xl] - sEy[ol][row][xl]) * idz);
+                return comb(0, cc, lb);
             };
             auto nb2 = [&](int yl, unsigned int cc) {  // new B_y on the face at tile row yl
-                const double lb = -((sEx[nl][yl][lane] - sEx[ol][yl][lane]) * g.inv_dx[2] -
-                                    (sEz[yl][lane + 1] - sEz[yl][lane]) * g.inv_dx[0]);
-                return (IN ? g0 * ld_at(In.f[6], cc) + g1 * ld_at(Bs.f[6], cc) : g1 * ld_at(Bs.f[6], cc)) + bdt * lb;
+                const R lb = -((sEx[nl][yl][lane] - sEx[ol][yl][lane]) * idz - (sEz[yl][lane + 1] - sEz[yl][lane]) * idx);
+                return comb(1, cc, lb);
             };
             auto nb3 = [&](int lvl, unsigned int cc) {  // new B_z on the z-face of level slot lvl
-                const double lb = -((sEy[lvl][row][lane + 1] - sEy[lvl][row][lane]) * g.inv_dx[0] -
-                                    (sEx[lvl][row + 1][lane] - sEx[lvl][row][lane]) * g.inv_dx[1]);
-                return (IN ? g0 * ld_at(In.f[7], cc) + g1 * ld_at(Bs.f[7], cc) : g1 * ld_at(Bs.f[7], cc)) + bdt * lb;
+                const R lb = -((sEy[lvl][row][lane + 1] - sEy[lvl][row][lane]) * idx -
+                               (sEx[lvl][row + 1][lane] - sEx[lvl][row][lane]) * idy);
+                return comb(2, cc, lb);
             };
-            const double b1 = nb1(lane, c);
-            const double b2 = nb2(row, c);
-            const double b3 = nb3(ol, c);
+            const R b1 = nb1(lane, c);
+            const R b2 = nb2(row, c);
+            const R b3 = nb3(ol, c);
             if (CFL) {
-                // the updated faces on the high side give the new B_cc of this cell
-                const double bx = 0.5 * (b1 + nb1(lane + 1, cx));
-                const double by = 0.5 * (b2 + nb2(row + 1, cy));
-                const double bz = 0.5 * (b3 + nb3(nl, cz));
+                // the updated faces on the high side give the new B_cc of this cell (FP64)
+                const double bx = 0.5 * ((double)b1 + (double)nb1(lane + 1, cx));
+                const double by = 0.5 * ((double)b2 + (double)nb2(row + 1, cy));
+                const double bz = 0.5 * ((double)b3 + (double)nb3(nl, cz));
                 double d = o[0];
                 if (d < P.rho_floor) d = P.rho_floor;
                 const double id = 1.0 / d;
-                const double v[3] = {o[1] * id, o[2] * id, o[3] * id};
+                const double v[3] = {(double)o[1] * id, (double)o[2] * id, (double)o[3] * id};
                 const double ke = 0.5 * d * ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
                 const double b2s = (bx * bx + by * by) + bz * bz;
-                double pr = (P.gamma - 1.0) * ((o[4] - ke) - 0.5 * b2s);
+                double pr = (P.gamma - 1.0) * ((oE - ke) - 0.5 * b2s);
                 if (pr < P.p_floor) pr = P.p_floor;
                 const double bd[3] = {bx, by, bz};
 #pragma unroll
@@ -518,11 +533,13 @@ __global__ __launch_bounds__(TX* TY2) void k_ct_update(Geo g, MhdParams P, CtArg
                 }
             }
             // out never aliases in or base (the host rotates three registers)
+            stT(a.out.rho, c, o[0]);
 #pragma unroll
-            for (int v = 0; v < 5; ++v) st_at(Out[v], c, o[v]);
-            st_at(Out[5], c, b1);
-            st_at(Out[6], c, b2);
-            st_at(Out[7], c, b3);
+            for (int v = 0; v < 3; ++v) stT(a.out.m[v], c, o[1 + v]);
+            stT(a.out.E, c, oE);
+            stT(a.out.b[0], c, b1);
+            stT(a.out.b[1], c, b2);
+            stT(a.out.b[2], c, b3);
         }
         __syncthreads();
         lv ^= 1;
@@ -542,6 +559,40 @@ __global__ __launch_bounds__(TX* TY2) void k_ct_update(Geo g, MhdParams P, CtArg
 }
 
 // ----------------------------------------------------------------------------------
+// FP32-bulk register <-> canonical FP64 state
+// ----------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_pack_fp32(long long n, const double* __restrict__ canon,
+                                                      RegView<float> r)
+{
+    const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= n) return;
+    r.rho[c] = (float)canon[c];
+    r.m[0][c] = (float)canon[n + c];
+    r.m[1][c] = (float)canon[2 * n + c];
+    r.m[2][c] = (float)canon[3 * n + c];
+    r.E[c] = canon[4 * n + c];
+    r.b[0][c] = (float)canon[5 * n + c];
+    r.b[1][c] = (float)canon[6 * n + c];
+    r.b[2][c] = (float)canon[7 * n + c];
+}
+
+__global__ __launch_bounds__(kBlock) void k_unpack_fp32(long long n, RegView<float> r,
+                                                        double* __restrict__ canon)
+{
+    const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= n) return;
+    canon[c] = r.rho[c];
+    canon[n + c] = r.m[0][c];
+    canon[2 * n + c] = r.m[1][c];
+    canon[3 * n + c] = r.m[2][c];
+    canon[4 * n + c] = r.E[c];
+    canon[5 * n + c] = r.b[0][c];
+    canon[6 * n + c] = r.b[1][c];
+    canon[7 * n + c] = r.b[2][c];
+}
+
+// ----------------------------------------------------------------------------------
 // launchers
 // ----------------------------------------------------------------------------------
 
@@ -558,49 +609,82 @@ FusedGrid fused_grid(const Geo& g, int kz)
     return fg;
 }
 
-template <int RECON, int RS>
-static hipError_t flux3(const Geo& g, const MhdParams& p, const FusedGrid& fg, const double* U,
-                        double* F, double* Rc, hipStream_t s)
+template <int RECON, int RS, class R>
+static hipError_t flux3(const Geo& g, const MhdParams& p, const FusedGrid& fg, void* U, void* F,
+                        void* Rc, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_flux3<RECON, RS>), dim3(fg.nblk), dim3(TX * TY), 0, s, g, p, U, F, Rc, fg.kz,
-                       fg.ntx, fg.nty, fg.nblk);
+    hipLaunchKernelGGL((k_flux3<RECON, RS, R>), dim3(fg.nblk), dim3(TX * TY), 0, s, g, p,
+                       reg_view<R>(U, g.n), (R*)F, (R*)Rc, fg.kz, fg.ntx, fg.nty, fg.nblk);
     return hipGetLastError();
 }
 
-hipError_t launch_mhd_flux3(const Geo& g, const MhdParams& p, const FusedGrid& fg, int recon,
-                            int riemann, const double* U, double* F, double* Rc, hipStream_t s)
+template <class R>
+static hipError_t flux3_any(const Geo& g, const MhdParams& p, const FusedGrid& fg, int recon,
+                            int riemann, void* U, void* F, void* Rc, hipStream_t s)
 {
     if (riemann == 1) {
-        if (recon == 0) return flux3<0, 1>(g, p, fg, U, F, Rc, s);
-        if (recon == 1) return flux3<1, 1>(g, p, fg, U, F, Rc, s);
-        return flux3<2, 1>(g, p, fg, U, F, Rc, s);
+        if (recon == 0) return flux3<0, 1, R>(g, p, fg, U, F, Rc, s);
+        if (recon == 1) return flux3<1, 1, R>(g, p, fg, U, F, Rc, s);
+        return flux3<2, 1, R>(g, p, fg, U, F, Rc, s);
     }
-    if (recon == 0) return flux3<0, 0>(g, p, fg, U, F, Rc, s);
-    if (recon == 1) return flux3<1, 0>(g, p, fg, U, F, Rc, s);
-    return flux3<2, 0>(g, p, fg, U, F, Rc, s);
+    if (recon == 0) return flux3<0, 0, R>(g, p, fg, U, F, Rc, s);
+    if (recon == 1) return flux3<1, 0, R>(g, p, fg, U, F, Rc, s);
+    return flux3<2, 0, R>(g, p, fg, U, F, Rc, s);
 }
 
-hipError_t launch_mhd_ct_update(const Geo& g, const MhdParams& p, const FusedGrid& fg,
-                                const double* in, const double* base, const double* F,
-                                const double* Rc, double* out, StageCoef coef, double* partial,
-                                double* dt_out, double cfl_scale, hipStream_t s)
+hipError_t launch_mhd_flux3(const Geo& g, const MhdParams& p, const FusedGrid& fg, bool fp32,
+                            int recon, int riemann, void* U, void* F, void* Rc, hipStream_t s)
 {
-    CtArgs a{in, base, F, Rc, out, partial, coef};
+    if (fp32) return flux3_any<float>(g, p, fg, recon, riemann, U, F, Rc, s);
+    return flux3_any<double>(g, p, fg, recon, riemann, U, F, Rc, s);
+}
+
+template <class R>
+static hipError_t ct_update(const Geo& g, const MhdParams& p, const FusedGrid& fg, void* in, void* base,
+                            const void* F, const void* Rc, void* out, StageCoef coef, double* partial,
+                            double* dt_out, double cfl_scale, hipStream_t s)
+{
+    CtArgs<R> a{reg_view<R>(in, g.n), reg_view<R>(base, g.n), (const R*)F, (const R*)Rc,
+                reg_view<R>(out, g.n), partial, coef};
     const bool use_in = coef.g0 != 0.0 || p.gacc[0] != 0.0 || p.gacc[1] != 0.0 || p.gacc[2] != 0.0;
     const dim3 gr(fg.nblk2), bl(TX * TY2);
     if (dt_out) {
         if (use_in)
-            hipLaunchKernelGGL((k_ct_update<true, true>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty2, fg.nblk2);
+            hipLaunchKernelGGL((k_ct_update<true, true, R>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty2, fg.nblk2);
         else
-            hipLaunchKernelGGL((k_ct_update<true, false>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty2, fg.nblk2);
+            hipLaunchKernelGGL((k_ct_update<true, false, R>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty2, fg.nblk2);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         return launch_min_final(partial, fg.nblk2, cfl_scale, dt_out, s);
     }
     if (use_in)
-        hipLaunchKernelGGL((k_ct_update<false, true>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty2, fg.nblk2);
+        hipLaunchKernelGGL((k_ct_update<false, true, R>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty2, fg.nblk2);
     else
-        hipLaunchKernelGGL((k_ct_update<false, false>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty2, fg.nblk2);
+        hipLaunchKernelGGL((k_ct_update<false, false, R>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty2, fg.nblk2);
+    return hipGetLastError();
+}
+
+hipError_t launch_mhd_ct_update(const Geo& g, const MhdParams& p, const FusedGrid& fg, bool fp32,
+                                void* in, void* base, const void* F, const void* Rc, void* out,
+                                StageCoef coef, double* partial, double* dt_out, double cfl_scale,
+                                hipStream_t s)
+{
+    if (fp32)
+        return ct_update<float>(g, p, fg, in, base, F, Rc, out, coef, partial, dt_out, cfl_scale, s);
+    return ct_update<double>(g, p, fg, in, base, F, Rc, out, coef, partial, dt_out, cfl_scale, s);
+}
+
+hipError_t launch_pack_fp32(const Geo& g, const double* canon, void* reg, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pack_fp32, dim3(blocks_for(g.n)), dim3(kBlock), 0, s, g.n, canon,
+                       reg_view<float>(reg, g.n));
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_fp32(const Geo& g, const void* reg, double* canon, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_unpack_fp32, dim3(blocks_for(g.n)), dim3(kBlock), 0, s, g.n,
+                       reg_view<float>(const_cast<void*>(reg), g.n), canon);
     return hipGetLastError();
 }
 

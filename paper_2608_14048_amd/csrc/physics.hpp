@@ -5,17 +5,23 @@
 // Face frame: for a sweep along direction d the frame is (n, t1, t2) = (d, d+1, d+2)
 // cyclic, so it stays right handed.  A face-frame MHD state is
 // (rho, v_n, v_t1, v_t2, p, B_t1, B_t2) with the normal field B_n taken from the face.
+//
+// Every function is templated on the real type R: double for the FP64 path, float for
+// the FP32-bulk path (where reciprocals and square roots use the single-instruction
+// hardware approximations; FP64 keeps IEEE division and square root).
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace mhd {
 
+template <class R>
 struct Prim7 {
-    double d, vn, vt1, vt2, p, bt1, bt2;
+    R d, vn, vt1, vt2, p, bt1, bt2;
 };
+template <class R>
 struct Flux7 {
-    double d, mn, mt1, mt2, e, bt1, bt2;
+    R d, mn, mt1, mt2, e, bt1, bt2;
 };
 struct Prim4 {
     double d, vn, vt1, vt2;
@@ -25,87 +31,121 @@ struct Flux4 {
 };
 
 // ----------------------------------------------------------------------------------
+// scalar helpers per precision
+// ----------------------------------------------------------------------------------
+
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
+__device__ __forceinline__ float sqrt_r(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double abs_r(double x) { return fabs(x); }
+__device__ __forceinline__ float abs_r(float x) { return fabsf(x); }
+__device__ __forceinline__ double min_r(double a, double b) { return fmin(a, b); }
+__device__ __forceinline__ float min_r(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ double max_r(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ float max_r(float a, float b) { return fmaxf(a, b); }
+// a / b: IEEE division in FP64, a times the hardware reciprocal in FP32
+__device__ __forceinline__ double div_r(double a, double b) { return a / b; }
+__device__ __forceinline__ float div_r(float a, float b) { return a * rcp(b); }
+
+// ----------------------------------------------------------------------------------
 // reconstruction of one scalar on the face between cells s[2] and s[3]
 // ----------------------------------------------------------------------------------
 
 // van Leer's monotonized harmonic mean of the one-sided differences.
-__device__ __forceinline__ double slope_vl(double am, double a0, double ap)
+template <class R>
+__device__ __forceinline__ R slope_vl(R am, R a0, R ap)
 {
-    const double dm = a0 - am, dp = ap - a0;
-    const double pr = dm * dp;
-    return pr > 0.0 ? 2.0 * pr / (dm + dp) : 0.0;
+    const R dm = a0 - am, dp = ap - a0;
+    const R pr = dm * dp;
+    return pr > R(0) ? div_r(R(2) * pr, dm + dp) : R(0);
 }
 
 // Colella-Woodward limited central slope of the middle cell.
-__device__ __forceinline__ double cw_slope(double am, double a0, double ap)
+template <class R>
+__device__ __forceinline__ R cw_slope(R am, R a0, R ap)
 {
-    const double dm = a0 - am, dp = ap - a0;
-    if (!(dm * dp > 0.0)) return 0.0;
-    const double c = 0.5 * (ap - am);
-    const double lim = fmin(fabs(c), fmin(2.0 * fabs(dm), 2.0 * fabs(dp)));
-    return c > 0.0 ? lim : -lim;
-}
-
-// Colella-Woodward monotonisation of a parabola (centre a, edges lo, hi).
-__device__ __forceinline__ void cw_limit(double a, double& lo, double& hi)
-{
-    if ((hi - a) * (a - lo) <= 0.0) {
-        lo = a;
-        hi = a;
-        return;
-    }
-    const double da = hi - lo;
-    const double a6 = 6.0 * (a - 0.5 * (lo + hi));
-    const double da2 = da * da;
-    if (da * a6 > da2)
-        lo = 3.0 * a - 2.0 * hi;
-    else if (-da2 > da * a6)
-        hi = 3.0 * a - 2.0 * lo;
-}
-
-template <int RECON>
-__device__ __forceinline__ void face_states(const double* s, double& aL, double& aR);
-
-template <>
-__device__ __forceinline__ void face_states<0>(const double* s, double& aL, double& aR)
-{
-    aL = s[2];
-    aR = s[3];
-}
-
-template <>
-__device__ __forceinline__ void face_states<1>(const double* s, double& aL, double& aR)
-{
-    aL = s[2] + 0.5 * slope_vl(s[1], s[2], s[3]);
-    aR = s[3] - 0.5 * slope_vl(s[2], s[3], s[4]);
+    const R dm = a0 - am, dp = ap - a0;
+    if (!(dm * dp > R(0))) return R(0);
+    const R c = R(0.5) * (ap - am);
+    const R lim = min_r(abs_r(c), min_r(R(2) * abs_r(dm), R(2) * abs_r(dp)));
+    return c > R(0) ? lim : -lim;
 }
 
 // Colella-Woodward interface value between cells a0 and a1 from their limited slopes
 // (the fourth-order average, monotonised through the slopes).
-__device__ __forceinline__ double cw_interface(double a0, double a1, double m0, double m1)
+template <class R>
+__device__ __forceinline__ R cw_interface(R a0, R a1, R m0, R m1)
 {
-    constexpr double kSixth = 1.0 / 6.0;
-    return a0 + 0.5 * (a1 - a0) - (m1 - m0) * kSixth;
+    return a0 + R(0.5) * (a1 - a0) - (m1 - m0) * R(1.0 / 6.0);
 }
 
-// PPM: the three interface values around the two cells next to the face are shared.
-template <>
-__device__ __forceinline__ void face_states<2>(const double* s, double& aL, double& aR)
+// Colella-Woodward monotonisation of a parabola (centre a, edges lo, hi).
+template <class R>
+__device__ __forceinline__ void cw_limit(R a, R& lo, R& hi)
 {
-    const double m1 = cw_slope(s[0], s[1], s[2]);
-    const double m2 = cw_slope(s[1], s[2], s[3]);
-    const double m3 = cw_slope(s[2], s[3], s[4]);
-    const double m4 = cw_slope(s[3], s[4], s[5]);
-    const double i0 = cw_interface(s[1], s[2], m1, m2);  // a_{f-3/2}
-    const double i1 = cw_interface(s[2], s[3], m2, m3);  // a_{f-1/2}
-    const double i2 = cw_interface(s[3], s[4], m3, m4);  // a_{f+1/2}
-    double lo = i0, hi = i1;
-    cw_limit(s[2], lo, hi);
-    aL = hi;
-    lo = i1;
-    hi = i2;
-    cw_limit(s[3], lo, hi);
-    aR = lo;
+    if ((hi - a) * (a - lo) <= R(0)) {
+        lo = a;
+        hi = a;
+        return;
+    }
+    const R da = hi - lo;
+    const R a6 = R(6) * (a - R(0.5) * (lo + hi));
+    const R da2 = da * da;
+    if (da * a6 > da2)
+        lo = R(3) * a - R(2) * hi;
+    else if (-da2 > da * a6)
+        hi = R(3) * a - R(2) * lo;
+}
+
+template <int RECON, class R>
+struct FaceStates;
+
+template <class R>
+struct FaceStates<0, R> {
+    __device__ static void get(const R* s, R& aL, R& aR)
+    {
+        aL = s[2];
+        aR = s[3];
+    }
+};
+
+template <class R>
+struct FaceStates<1, R> {
+    __device__ static void get(const R* s, R& aL, R& aR)
+    {
+        aL = s[2] + R(0.5) * slope_vl(s[1], s[2], s[3]);
+        aR = s[3] - R(0.5) * slope_vl(s[2], s[3], s[4]);
+    }
+};
+
+// PPM: the three interface values around the two cells next to the face are shared.
+template <class R>
+struct FaceStates<2, R> {
+    __device__ static void get(const R* s, R& aL, R& aR)
+    {
+        const R m1 = cw_slope(s[0], s[1], s[2]);
+        const R m2 = cw_slope(s[1], s[2], s[3]);
+        const R m3 = cw_slope(s[2], s[3], s[4]);
+        const R m4 = cw_slope(s[3], s[4], s[5]);
+        const R i0 = cw_interface(s[1], s[2], m1, m2);  // a_{f-3/2}
+        const R i1 = cw_interface(s[2], s[3], m2, m3);  // a_{f-1/2}
+        const R i2 = cw_interface(s[3], s[4], m3, m4);  // a_{f+1/2}
+        R lo = i0, hi = i1;
+        cw_limit(s[2], lo, hi);
+        aL = hi;
+        lo = i1;
+        hi = i2;
+        cw_limit(s[3], lo, hi);
+        aR = lo;
+    }
+};
+
+// Face states of the six cells s[0..5] around the face between s[2] and s[3].
+template <int RECON, class R>
+__device__ __forceinline__ void face_states(const R* s, R& aL, R& aR)
+{
+    FaceStates<RECON, R>::get(s, aL, aR);
 }
 
 // ----------------------------------------------------------------------------------
@@ -113,32 +153,34 @@ __device__ __forceinline__ void face_states<2>(const double* s, double& aL, doub
 // ----------------------------------------------------------------------------------
 
 // Fast magnetosonic speed along a direction with field component bd; b2 = |B|^2.
-__device__ __forceinline__ double fast_speed(double gam, double d, double p, double b2, double bd)
+template <class R>
+__device__ __forceinline__ R fast_speed(R gam, R d, R p, R b2, R bd)
 {
-    const double id = 1.0 / d;
-    const double a2 = gam * p * id;
-    const double s = a2 + b2 * id;
-    const double disc = fmax(s * s - 4.0 * a2 * (bd * bd) * id, 0.0);
-    return sqrt(0.5 * (s + sqrt(disc)));
+    const R id = rcp(d);
+    const R a2 = gam * p * id;
+    const R s = a2 + b2 * id;
+    const R disc = max_r(s * s - R(4) * a2 * (bd * bd) * id, R(0));
+    return sqrt_r(R(0.5) * (s + sqrt_r(disc)));
 }
 
 // Conserved vector, physical flux and total pressure of one face-frame state.
+template <class R>
 struct Side {
-    double U[7];
-    double F[7];
-    double pt, vb, cf;
+    R U[7];
+    R F[7];
+    R pt, vb, cf;
 };
 
-__device__ __forceinline__ void side_of(const Prim7& w, double bn, double gam, double gm1inv,
-                                        Side& s)
+template <class R>
+__device__ __forceinline__ void side_of(const Prim7<R>& w, R bn, R gam, R gm1inv, Side<R>& s)
 {
-    const double bt2 = w.bt1 * w.bt1 + w.bt2 * w.bt2;
-    const double b2 = bn * bn + bt2;
-    const double v2 = w.vn * w.vn + (w.vt1 * w.vt1 + w.vt2 * w.vt2);
-    const double pt = w.p + 0.5 * b2;
-    const double E = w.p * gm1inv + 0.5 * w.d * v2 + 0.5 * b2;
-    const double vb = w.vn * bn + (w.vt1 * w.bt1 + w.vt2 * w.bt2);
-    const double mn = w.d * w.vn;
+    const R bt2 = w.bt1 * w.bt1 + w.bt2 * w.bt2;
+    const R b2 = bn * bn + bt2;
+    const R v2 = w.vn * w.vn + (w.vt1 * w.vt1 + w.vt2 * w.vt2);
+    const R pt = w.p + R(0.5) * b2;
+    const R E = w.p * gm1inv + R(0.5) * w.d * v2 + R(0.5) * b2;
+    const R vb = w.vn * bn + (w.vt1 * w.bt1 + w.vt2 * w.bt2);
+    const R mn = w.d * w.vn;
     s.U[0] = w.d;
     s.U[1] = mn;
     s.U[2] = w.d * w.vt1;
@@ -158,24 +200,26 @@ __device__ __forceinline__ void side_of(const Prim7& w, double bn, double gam, d
     s.cf = fast_speed(gam, w.d, w.p, b2, bn);
 }
 
-__device__ __forceinline__ void to_flux(const double* a, Flux7& f)
+template <class R>
+__device__ __forceinline__ void to_flux(const R* a, Flux7<R>& f)
 {
     f.d = a[0]; f.mn = a[1]; f.mt1 = a[2]; f.mt2 = a[3]; f.e = a[4]; f.bt1 = a[5]; f.bt2 = a[6];
 }
 
 // HLLE with the outer bounds S_L = min(u) - max(c_f), S_R = max(u) + max(c_f).
-__device__ __forceinline__ void riemann_hlle(const Prim7& L, const Prim7& R, double bn,
-                                             double gam, double gm1inv, Flux7& f)
+template <class R>
+__device__ __forceinline__ void riemann_hlle(const Prim7<R>& L, const Prim7<R>& Rt, R bn, R gam,
+                                             R gm1inv, Flux7<R>& f)
 {
-    Side a, b;
+    Side<R> a, b;
     side_of(L, bn, gam, gm1inv, a);
-    side_of(R, bn, gam, gm1inv, b);
-    const double cmax = fmax(a.cf, b.cf);
-    const double sl = fmin(L.vn, R.vn) - cmax;
-    const double sr = fmax(L.vn, R.vn) + cmax;
-    const double bm = fmin(sl, 0.0), bp = fmax(sr, 0.0);
-    const double inv = 1.0 / (bp - bm);
-    double o[7];
+    side_of(Rt, bn, gam, gm1inv, b);
+    const R cmax = max_r(a.cf, b.cf);
+    const R sl = min_r(L.vn, Rt.vn) - cmax;
+    const R sr = max_r(L.vn, Rt.vn) + cmax;
+    const R bm = min_r(sl, R(0)), bp = max_r(sr, R(0));
+    const R inv = rcp(bp - bm);
+    R o[7];
 #pragma unroll
     for (int q = 0; q < 7; ++q) o[q] = (bp * a.F[q] - bm * b.F[q] + bp * bm * (b.U[q] - a.U[q])) * inv;
     to_flux(o, f);
@@ -184,23 +228,25 @@ __device__ __forceinline__ void riemann_hlle(const Prim7& L, const Prim7& R, dou
 // One side of the HLLD star region: density behind the fast wave, transverse velocity
 // and field from the jump conditions (kept at their outer values where the
 // denominator degenerates), and the energy from the energy jump condition.
+template <class R>
 struct Star {
-    double d, vt1, vt2, bt1, bt2, e, vb, sqd;
+    R d, vt1, vt2, bt1, bt2, e, vb, sqd;
 };
 
-__device__ __forceinline__ void star_of(const Prim7& w, const Side& s, double bn, double S,
-                                        double SM, double pts, double eps, Star& o)
+template <class R>
+__device__ __forceinline__ void star_of(const Prim7<R>& w, const Side<R>& s, R bn, R S, R SM, R pts,
+                                        R eps, Star<R>& o)
 {
-    const double du = S - w.vn;
-    const double ds = 1.0 / (S - SM);
+    const R du = S - w.vn;
+    const R ds = rcp(S - SM);
     o.d = w.d * du * ds;
-    const double den = w.d * du * (S - SM) - bn * bn;
-    if (fabs(den) <= eps * pts) {
+    const R den = w.d * du * (S - SM) - bn * bn;
+    if (abs_r(den) <= eps * pts) {
         o.vt1 = w.vt1; o.vt2 = w.vt2; o.bt1 = w.bt1; o.bt2 = w.bt2;
     } else {
-        const double r = 1.0 / den;
-        const double cv = bn * (SM - w.vn) * r;
-        const double cb = (w.d * du * du - bn * bn) * r;
+        const R r = rcp(den);
+        const R cv = bn * (SM - w.vn) * r;
+        const R cb = (w.d * du * du - bn * bn) * r;
         o.vt1 = w.vt1 - w.bt1 * cv;
         o.vt2 = w.vt2 - w.bt2 * cv;
         o.bt1 = w.bt1 * cb;
@@ -208,69 +254,70 @@ __device__ __forceinline__ void star_of(const Prim7& w, const Side& s, double bn
     }
     o.vb = SM * bn + (o.vt1 * o.bt1 + o.vt2 * o.bt2);
     o.e = (du * s.U[4] - s.pt * w.vn + pts * SM + bn * (s.vb - o.vb)) * ds;
-    o.sqd = sqrt(o.d);
+    o.sqd = sqrt_r(o.d);
 }
 
 // Miyoshi & Kusano (2005) five-wave HLLD flux.
-__device__ __forceinline__ void riemann_hlld(const Prim7& L, const Prim7& R, double bn,
-                                             double gam, double gm1inv, double eps, Flux7& f)
+template <class R>
+__device__ __forceinline__ void riemann_hlld(const Prim7<R>& L, const Prim7<R>& Rt, R bn, R gam,
+                                             R gm1inv, R eps, Flux7<R>& f)
 {
-    Side a, b;
+    Side<R> a, b;
     side_of(L, bn, gam, gm1inv, a);
-    side_of(R, bn, gam, gm1inv, b);
-    const double cmax = fmax(a.cf, b.cf);
-    const double sl = fmin(L.vn, R.vn) - cmax;
-    const double sr = fmax(L.vn, R.vn) + cmax;
-    if (sl > 0.0) { to_flux(a.F, f); return; }
-    if (sr < 0.0) { to_flux(b.F, f); return; }
+    side_of(Rt, bn, gam, gm1inv, b);
+    const R cmax = max_r(a.cf, b.cf);
+    const R sl = min_r(L.vn, Rt.vn) - cmax;
+    const R sr = max_r(L.vn, Rt.vn) + cmax;
+    if (sl > R(0)) { to_flux(a.F, f); return; }
+    if (sr < R(0)) { to_flux(b.F, f); return; }
 
-    const double ml = L.d * (sl - L.vn), mr = R.d * (sr - R.vn);  // mass fluxes into the fan
-    const double iden = 1.0 / (mr - ml);
-    const double SM = (mr * R.vn - ml * L.vn - b.pt + a.pt) * iden;
-    const double pts = (mr * a.pt - ml * b.pt + ml * mr * (R.vn - L.vn)) * iden;
+    const R ml = L.d * (sl - L.vn), mr = Rt.d * (sr - Rt.vn);  // mass fluxes into the fan
+    const R iden = rcp(mr - ml);
+    const R SM = (mr * Rt.vn - ml * L.vn - b.pt + a.pt) * iden;
+    const R pts = (mr * a.pt - ml * b.pt + ml * mr * (Rt.vn - L.vn)) * iden;
 
-    Star x, y;
+    Star<R> x, y;
     star_of(L, a, bn, sl, SM, pts, eps, x);
-    star_of(R, b, bn, sr, SM, pts, eps, y);
-    const double slst = SM - fabs(bn) / x.sqd;
-    const double srst = SM + fabs(bn) / y.sqd;
+    star_of(Rt, b, bn, sr, SM, pts, eps, y);
+    const R slst = SM - div_r(abs_r(bn), x.sqd);
+    const R srst = SM + div_r(abs_r(bn), y.sqd);
 
     // U* on each side
-    double ul[7] = {x.d, x.d * SM, x.d * x.vt1, x.d * x.vt2, x.e, x.bt1, x.bt2};
-    double ur[7] = {y.d, y.d * SM, y.d * y.vt1, y.d * y.vt2, y.e, y.bt1, y.bt2};
-    double o[7];
-    if (slst >= 0.0) {
+    R ul[7] = {x.d, x.d * SM, x.d * x.vt1, x.d * x.vt2, x.e, x.bt1, x.bt2};
+    R ur[7] = {y.d, y.d * SM, y.d * y.vt1, y.d * y.vt2, y.e, y.bt1, y.bt2};
+    R o[7];
+    if (slst >= R(0)) {
 #pragma unroll
         for (int q = 0; q < 7; ++q) o[q] = a.F[q] + sl * (ul[q] - a.U[q]);
         to_flux(o, f);
         return;
     }
-    if (srst < 0.0) {
+    if (srst < R(0)) {
 #pragma unroll
         for (int q = 0; q < 7; ++q) o[q] = b.F[q] + sr * (ur[q] - b.U[q]);
         to_flux(o, f);
         return;
     }
     // between the two Alfven waves
-    const bool left = SM >= 0.0;
-    const Star& st = left ? x : y;
-    const double* us = left ? ul : ur;
-    const double S = left ? sl : sr;
-    const double Sst = left ? slst : srst;
-    const Side& sd = left ? a : b;
-    double uss[7];
+    const bool left = SM >= R(0);
+    const Star<R>& st = left ? x : y;
+    const R* us = left ? ul : ur;
+    const R S = left ? sl : sr;
+    const R Sst = left ? slst : srst;
+    const Side<R>& sd = left ? a : b;
+    R uss[7];
     if (bn * bn <= eps * pts) {
 #pragma unroll
         for (int q = 0; q < 7; ++q) uss[q] = us[q];
     } else {
-        const double sg = bn > 0.0 ? 1.0 : -1.0;
-        const double inv = 1.0 / (x.sqd + y.sqd);
-        const double v1 = (x.sqd * x.vt1 + y.sqd * y.vt1 + (y.bt1 - x.bt1) * sg) * inv;
-        const double v2 = (x.sqd * x.vt2 + y.sqd * y.vt2 + (y.bt2 - x.bt2) * sg) * inv;
-        const double b1 = (x.sqd * y.bt1 + y.sqd * x.bt1 + x.sqd * y.sqd * (y.vt1 - x.vt1) * sg) * inv;
-        const double b2 = (x.sqd * y.bt2 + y.sqd * x.bt2 + x.sqd * y.sqd * (y.vt2 - x.vt2) * sg) * inv;
-        const double vbss = SM * bn + (v1 * b1 + v2 * b2);
-        const double ess = left ? x.e - x.sqd * (x.vb - vbss) * sg : y.e + y.sqd * (y.vb - vbss) * sg;
+        const R sg = bn > R(0) ? R(1) : R(-1);
+        const R inv = rcp(x.sqd + y.sqd);
+        const R v1 = (x.sqd * x.vt1 + y.sqd * y.vt1 + (y.bt1 - x.bt1) * sg) * inv;
+        const R v2 = (x.sqd * x.vt2 + y.sqd * y.vt2 + (y.bt2 - x.bt2) * sg) * inv;
+        const R b1 = (x.sqd * y.bt1 + y.sqd * x.bt1 + x.sqd * y.sqd * (y.vt1 - x.vt1) * sg) * inv;
+        const R b2 = (x.sqd * y.bt2 + y.sqd * x.bt2 + x.sqd * y.sqd * (y.vt2 - x.vt2) * sg) * inv;
+        const R vbss = SM * bn + (v1 * b1 + v2 * b2);
+        const R ess = left ? x.e - x.sqd * (x.vb - vbss) * sg : y.e + y.sqd * (y.vb - vbss) * sg;
         uss[0] = st.d; uss[1] = st.d * SM; uss[2] = st.d * v1; uss[3] = st.d * v2;
         uss[4] = ess; uss[5] = b1; uss[6] = b2;
     }
@@ -280,7 +327,7 @@ __device__ __forceinline__ void riemann_hlld(const Prim7& L, const Prim7& R, dou
 }
 
 // ----------------------------------------------------------------------------------
-// isothermal gas and pressureless dust
+// isothermal gas and pressureless dust (FP64)
 // ----------------------------------------------------------------------------------
 
 __device__ __forceinline__ void riemann_iso_hlle(const Prim4& L, const Prim4& R, double cs,

@@ -38,9 +38,10 @@ def test_workspace_and_validation():
     g, p, s = _ws()
     nb = B.mhd_workspace_bytes(g, p, s)
     assert nb >= 2 * 8 * 512 * 8  # two FP64 registers of 8 fields at least
-    # bigger grid, bigger workspace
+    # bigger grid, bigger workspace; the FP32-bulk form needs less
     g2, p2, s2 = _ws((16, 8, 8))
     assert B.mhd_workspace_bytes(g2, p2, s2) > nb
+    assert B.mhd_workspace_bytes(*_ws(prec="fp32_bulk")) < nb
     bad = [
         dict(shape=(0, 8, 8)),
         dict(courant=0.0),
@@ -57,6 +58,8 @@ def test_workspace_and_validation():
         dict(eos="isothermal_hydro", tstop=(1.0,), integ="imex2p", riemann="hlle", recon="ppm"),
         dict(eos="isothermal_hydro", tstop=(), integ="imex2p", riemann="hlle"),
         dict(eos="isothermal_hydro", tstop=(1.0,) * 17, integ="imex2p", riemann="hlle"),
+        dict(eos="isothermal_hydro", tstop=(1.0,), integ="imex2p", riemann="hlle", prec="fp32_bulk"),
+        dict(shape=(1024, 1024, 512)),                            # 2^29 cells: beyond 32-bit offsets
     ]
     for kw in unsupported:
         shape = kw.pop("shape", (8, 8, 8))

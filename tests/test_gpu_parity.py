@@ -363,3 +363,92 @@ def test_nonfinite_state_is_reported():
         assert e.value.code == -5
     finally:
         pr.close()
+
+
+# ----------------------------------------------------------------------------------
+# FP32-bulk form (FP64 total energy): errors against the FP64 oracle, stated
+# ----------------------------------------------------------------------------------
+
+FP32_STEP_TOL = 2e-6     # one step, per conserved class (R13 scale)
+FP32_RUN_L1_TOL = 1e-4   # 100 steps, relative L1 per class (measured 1.3e-5 .. 3.4e-5)
+
+
+def l1_rel(pair, got, ref):
+    n = int(np.prod(pair.shape))
+    g = got.reshape(-1, n)
+    r = ref.reshape(-1, n)
+    rows = {"rho": [0], "M": [1, 2, 3], "E": [4], "B": [5, 6, 7]}
+    return {k: float(np.abs(g[v] - r[v]).sum() / np.abs(r[v]).sum()) for k, v in rows.items()}
+
+
+class Pair32(Pair):
+    def __init__(self, shape, **kw):
+        super().__init__(shape, **kw)
+        self.sim.close()
+        kw_s = dict(recon=kw.get("recon", "plm"), riemann=kw.get("riemann", "hlld"),
+                    integ=kw.get("integ", "vl2"), courant=kw.get("courant", 0.3), prec="fp32_bulk")
+        self.sim = B.Sim(shape, kw.get("length", (1.0, 1.0, 1.0)),
+                         physics=dict(gamma=kw.get("gamma", 5.0 / 3.0)), scheme=kw_s)
+
+
+@pytest.mark.parametrize("recon,riemann", [("ppm", "hlld"), ("plm", "hlle")])
+def test_fp32_bulk_one_step_against_oracle(recon, riemann):
+    st = I.turbulence(32, seed=5)
+    pr = Pair32((32, 32, 32), recon=recon, riemann=riemann)
+    try:
+        pr.sim.set_state(st)
+        back = pr.sim.state()
+        nc = 32 ** 3
+        # E is kept in FP64; every other field is rounded to FP32 once
+        assert np.array_equal(back[4 * nc:5 * nc], st[4 * nc:5 * nc])
+        assert np.abs(back - st).max() <= 6e-8 * np.abs(st).max()
+        dt = oracle.dt_cfl(pr.cfg, st)
+        assert abs(pr.sim.dt_cfl() - dt) <= 1e-14 * dt
+        pr.sim.step(dt)
+        ref = oracle.step(pr.cfg, st, dt)
+        got = pr.sim.state()
+        e = class_errors(pr, got, ref)
+        _say(f"  fp32-bulk {recon}/{riemann} one step: {e}  L1 {l1_rel(pr, got, ref)}")
+        assert max(e.values()) <= FP32_STEP_TOL
+    finally:
+        pr.close()
+
+
+def test_fp32_bulk_hundred_steps_l1_against_oracle():
+    """The 64^3 turbulence recipe, 100 steps on the oracle's dt sequence: relative L1
+    error of every conserved class against the FP64 oracle."""
+    st = I.turbulence(64, seed=1)
+    pr = Pair32((64, 64, 64), recon="ppm", riemann="hlld")
+    try:
+        ref, got = run_both(pr, st, 100, check_dt=False)
+        e = l1_rel(pr, got, ref)
+        _say(f"  fp32-bulk turb64 x100: relative L1 {e}  max-class {class_errors(pr, got, ref)}")
+        assert max(e.values()) <= FP32_RUN_L1_TOL
+    finally:
+        pr.close()
+
+
+def test_fp32_bulk_invariants():
+    st = I.turbulence(48, seed=6)
+    pr = Pair32((48, 48, 48), recon="ppm", riemann="hlld")
+    try:
+        pr.sim.set_state(st)
+        d0 = pr.sim.diagnostics()
+        pr.sim.run(20)
+        d1 = pr.sim.diagnostics()
+        bmax = np.abs(st[5 * 48 ** 3:]).max() * 48
+        _say(f"  fp32-bulk max|divB| {d1[8]:.3e} (field/dx {bmax:.3e}); dE/E {abs(d1[4] - d0[4]) / d0[4]:.2e}")
+        assert d1[8] < 1e-5 * bmax
+        # the energy is stored in FP64 and its flux differences telescope in FP64
+        assert abs(d1[4] - d0[4]) < 1e-12 * d0[4]
+        assert abs(d1[0] - d0[0]) < 1e-6 * d0[0]
+        assert np.all(np.abs(d1[1:4] - d0[1:4]) < 1e-6 * d0[0])
+        # bitwise rerun
+        pr.sim.set_state(st)
+        pr.sim.run(3)
+        a = pr.sim.state()
+        pr.sim.set_state(st)
+        pr.sim.run(3)
+        assert np.array_equal(a, pr.sim.state())
+    finally:
+        pr.close()

@@ -11,8 +11,13 @@ HBM.  The metric counts each cell once per cycle (Mzone-cycles/s).
 Prints one JSON line.  Besides the throughput it reports the roofline of the kernel
 class that takes most device time (HIP events on the library's stream over the timed
 region) and the CPU oracle timed on this host on a bounded sample of the same workload.
+Side legs, each on its own workload and reported in its own object: the FP32-bulk form
+of the same run, the gas + 8 dust IMEX2P step at 192^3, and the RK2+PLM+HLLE oblique
+linear wave on a 512 x 512 x 256 box (the scheme and box of the paper's performance
+table).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--no-cpu-baseline]
+                       [--no-fp32] [--no-dust] [--no-paper-config]
 """
 from __future__ import annotations
 
@@ -45,6 +50,20 @@ KERNEL_ALGO = {
     "cfl": {"bytes": 8 * 8, "flops": 72},
 }
 
+# Gas + dust IMEX2P kernels (36 fields per state at 8 dust species, 27 of them momenta),
+# bytes per cell: every array the kernel needs read once, every array it produces
+# written once.  The step's own minimum (stage 1 reads u and writes U1, stage 2 reads
+# u and U1 and writes u) is 5 x 36 fields; the four launches move 342 fields.
+DUST_FIELDS, DUST_MOM = 36, 27
+DUST_STEP_ALGO_BYTES = 5 * DUST_FIELDS * 8
+DUST_KERNEL_ALGO = {
+    "dust_fluid_pass_stage1": {"bytes": 2 * DUST_FIELDS * 8},              # u in, X out
+    "dust_fluid_pass_stage2": {"bytes": 3 * DUST_FIELDS * 8},              # U1, u in, X out
+    "dust_drag_stage1": {"bytes": (DUST_FIELDS + DUST_MOM) * 8},           # X in, momenta out
+    "dust_drag_cfl_stage2": {"bytes": (2 * DUST_FIELDS + DUST_MOM) * 8},   # X, U1 in, momenta out
+    "cfl": {"bytes": DUST_FIELDS * 8},
+}
+
 WORKLOAD = "decaying MHD turbulence, periodic {n}^3, VL2+PPM+HLLD+CT, CFL 0.3, seed 0"
 
 
@@ -75,6 +94,119 @@ def measured_traffic(kernel: str, n_cells: int):
         return None
 
 
+def timed_run(sim, steps: int, warmup: int, dts_in=None):
+    """{dt = CFL step; step(dt)} warmup times, then steps times under HIP-event timing of
+    every launch.  With dts_in the given dt sequence (warm-up first) is stepped instead,
+    each step still reading its own CFL step.  Returns (seconds, per-class event times,
+    warm-up dts, timed dts)."""
+    import torch
+
+    warm, dts = [], []
+    for k in range(warmup):
+        dt = sim.dt_cfl()
+        dt = dts_in[k] if dts_in is not None else dt
+        sim.step(dt)
+        warm.append(dt)
+    torch.cuda.synchronize()
+    sim.timing(capacity=32 * steps + 64)
+    sim.timing_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        dt = sim.dt_cfl()
+        dt = dts_in[warmup + k] if dts_in is not None else dt
+        sim.step(dt)
+        dts.append(dt)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    times = sim.timing_read()
+    sim.timing(0)
+    return el, times, warm, dts
+
+
+def kernel_roofline(times, table, ncell, alu_peak=None):
+    """Roofline of the kernel class with the largest device time: achieved algorithmic
+    bytes (and flops, where the table has them) per average launch duration."""
+    dominant = max(times, key=lambda k: times[k][0])
+    total_ms, launches = times[dominant]
+    avg_s = total_ms / launches * 1e-3
+    work = table.get(dominant, {"bytes": 0})
+    gbs = work["bytes"] * ncell / avg_s / 1e9
+    f_hbm = gbs / HBM_PEAK_GBS
+    rf = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+          "frac": round(f_hbm, 4)}
+    f_alu = None
+    if alu_peak and "flops" in work:
+        tfl = work["flops"] * ncell / avg_s / 1e12
+        f_alu = tfl / alu_peak
+        if f_alu > f_hbm:
+            rf = {"bound": "alu", "achieved": round(tfl, 3), "peak": alu_peak, "unit": "TFLOP/s",
+                  "frac": round(f_alu, 4)}
+    rf.update({"traffic": measured_traffic(dominant, ncell), "kernel": dominant,
+               "avg_launch_ms": round(total_ms / launches, 4), "launches": launches,
+               "hbm_frac": round(f_hbm, 4)})
+    if f_alu is not None:
+        rf["alu_frac"] = round(f_alu, 4)
+    return rf
+
+
+def dust_leg(n: int, steps: int, warmup: int, seed: int = 0):
+    """Gas + 8 dust fluids, isothermal gas, IMEX2P with PLM, isothermal HLLE and
+    pressureless Rusanov, gas acceleration 0.05 x^, n^3 periodic, FP64."""
+    from paper_2608_14048_amd import Sim
+    from paper_2608_14048_amd import inputs as I
+
+    print(f"[bench] dust leg {n}^3", file=sys.stderr, flush=True)
+    state, ts = I.dust_drift(n, seed=seed)
+    sim = Sim((n, n, n), physics=dict(eos="isothermal_hydro", cs=1.0, tstop=tuple(ts),
+                                      gacc=(0.05, 0.0, 0.0)),
+              scheme=dict(recon="plm", riemann="hlle", integ="imex2p", courant=0.3))
+    sim.set_state(state)
+    el, times, _, _ = timed_run(sim, steps, warmup)
+    sim.close()
+    ncell = n ** 3
+    value = ncell * steps / el / 1e6
+    return {"workload": f"gas + 8 dust fluids, t_s log-spaced 1e-3..10, eps 0.01 each, "
+                        f"g = 0.05, periodic {n}^3, IMEX2P+PLM+HLLE/Rusanov, CFL 0.3, seed {seed}",
+            "value": round(value, 2), "unit": "Mzone-cycles/s", "dtype": "f64", "steps": steps,
+            "ms_per_step": round(el * 1e3 / steps, 4),
+            "roofline": kernel_roofline(times, DUST_KERNEL_ALGO, ncell),
+            "step_hbm_roofline": {"algo_bytes_per_zone_cycle": DUST_STEP_ALGO_BYTES,
+                                  "frac": round(value * 1e6 * DUST_STEP_ALGO_BYTES
+                                                / (HBM_PEAK_GBS * 1e9), 4)},
+            "kernel_ms_per_step": {k: round(v[0] / steps, 4) for k, v in sorted(times.items())}}
+
+
+PAPER_TABLE = {"A100 (FP64)": 300.0, "MI250X one GCD (FP64)": 250.0}
+
+
+def paper_config_leg(shape, steps: int, warmup: int, precisions=("fp64", "fp32_bulk")):
+    """The scheme and box of the paper's performance table: oblique linear fast wave,
+    RK2 + PLM + HLLE + CT, one block of shape cells; the paper's FP64 numbers on other
+    hardware are quoted as context."""
+    from paper_2608_14048_amd import Sim
+    from paper_2608_14048_amd import inputs as I
+
+    print(f"[bench] paper-configuration leg {shape}", file=sys.stderr, flush=True)
+    state, _ = I.linear_wave(amp=1e-6, along="box", shape=shape)
+    length = (shape[0] / shape[2], shape[1] / shape[2], 1.0)
+    ncell = shape[0] * shape[1] * shape[2]
+    out = {"workload": f"oblique linear fast wave, {shape[0]}x{shape[1]}x{shape[2]} "
+                       "periodic box, RK2+PLM+HLLE+CT, CFL 0.3, one block",
+           "paper_mzcps_context": PAPER_TABLE}
+    for prec in precisions:
+        sim = Sim(shape, length, scheme=dict(recon="plm", riemann="hlle", integ="rk2",
+                                             courant=0.3, prec=prec))
+        sim.set_state(state)
+        el, times, _, _ = timed_run(sim, steps, warmup)
+        sim.close()
+        out[prec] = {"value": round(ncell * steps / el / 1e6, 2), "unit": "Mzone-cycles/s",
+                     "steps": steps, "ms_per_step": round(el * 1e3 / steps, 4),
+                     "kernel_ms_per_step": {k: round(v[0] / steps, 4)
+                                            for k, v in sorted(times.items())}}
+    return out
+
+
 def cpu_baseline(n: int, state, max_seconds: float = 30.0):
     """The oracle as it stands on a bounded sample: as many steps of the same workload
     as fit in about max_seconds (at least one)."""
@@ -103,24 +235,13 @@ def fp32_leg(n, state, warm_dts, dts, ref64):
     sequence as the FP64 run (each step still reads its own CFL step, as in the FP64
     loop); reports its throughput and the relative L1 difference of each conserved
     class to the FP64 state after the same steps."""
-    import torch
-
     from paper_2608_14048_amd import Sim
 
     print("[bench] FP32-bulk leg", file=sys.stderr, flush=True)
     sim = Sim((n, n, n), scheme=dict(recon="ppm", riemann="hlld", integ="vl2", courant=0.3,
                                      prec="fp32_bulk"))
     sim.set_state(state)
-    for dt in warm_dts:
-        sim.dt_cfl()
-        sim.step(dt)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for dt in dts:
-        sim.dt_cfl()
-        sim.step(dt)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    el, times, _, _ = timed_run(sim, len(dts), len(warm_dts), list(warm_dts) + list(dts))
     got = sim.state(device=True).reshape(8, -1)
     ref = ref64.reshape(8, -1)
     rows = {"rho": [0], "M": [1, 2, 3], "E": [4], "B": [5, 6, 7]}
@@ -130,7 +251,8 @@ def fp32_leg(n, state, warm_dts, dts, ref64):
     return {"value": round(n ** 3 * steps / el / 1e6, 2), "unit": "Mzone-cycles/s",
             "ms_per_step": round(el * 1e3 / steps, 4), "dtype": "f32 (E in f64)",
             "l1_rel_vs_fp64": {k: float(f"{v:.3e}") for k, v in l1.items()},
-            "compared_after_steps": len(warm_dts) + steps}
+            "compared_after_steps": len(warm_dts) + steps,
+            "kernel_ms_per_step": {k: round(v[0] / steps, 4) for k, v in sorted(times.items())}}
 
 
 def main():
@@ -143,6 +265,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=25.0)
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-bulk leg")
+    ap.add_argument("--no-dust", action="store_true", help="skip the gas + dust leg")
+    ap.add_argument("--no-paper-config", action="store_true",
+                    help="skip the RK2+PLM+HLLE linear-wave leg")
+    ap.add_argument("--dust-n", type=int, default=192)
+    ap.add_argument("--paper-shape", type=int, nargs=3, default=(512, 512, 256))
+    ap.add_argument("--side-steps", type=int, default=50)
+    ap.add_argument("--side-warmup", type=int, default=5)
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 2 GiB device copy three times (the calibration "
                          "launch for HBM byte counters)")
@@ -175,52 +304,14 @@ def main():
 
     sim = Sim((n, n, n), scheme=dict(recon="ppm", riemann="hlld", integ="vl2", courant=0.3))
     sim.set_state(state)
-    print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
-    warm_dts = []
-    for _ in range(args.warmup):
-        dt = sim.dt_cfl()
-        sim.step(dt)
-        warm_dts.append(dt)
-    torch.cuda.synchronize()
-    # events around every launch of the timed region (16 launches per step at most)
-    sim.timing(capacity=32 * args.steps + 64)
-    sim.timing_read()
-    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
-    dts = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        dt = sim.dt_cfl()
-        sim.step(dt)
-        dts.append(dt)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    times = sim.timing_read()
-    sim.timing(0)
-    elapsed = t1 - t0
+    print(f"[bench] {args.warmup} warm-up + {args.steps} timed steps", file=sys.stderr, flush=True)
+    elapsed, times, warm_dts, dts = timed_run(sim, args.steps, args.warmup)
     ncell = n ** 3
     value = ncell * args.steps / elapsed / 1e6
     ms_per_step = elapsed * 1e3 / args.steps
-
     # roofline of the kernel class with the largest device time, against the resource
     # it is closer to saturating (HBM bytes or FP64 vector flops)
-    dominant = max(times, key=lambda k: times[k][0])
-    total_ms, launches = times[dominant]
-    avg_s = total_ms / launches * 1e-3
-    work = KERNEL_ALGO.get(dominant, {"bytes": 0, "flops": 0})
-    gbs = work["bytes"] * ncell / avg_s / 1e9
-    tfl = work["flops"] * ncell / avg_s / 1e12
-    f_hbm, f_alu = gbs / HBM_PEAK_GBS, tfl / FP64_VECTOR_PEAK_TFLOPS
-    traffic = measured_traffic(dominant, ncell)
-    if f_alu > f_hbm:
-        roofline = {"bound": "alu", "achieved": round(tfl, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(f_alu, 4)}
-    else:
-        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(f_hbm, 4)}
-    roofline.update({"traffic": traffic, "kernel": dominant,
-                     "avg_launch_ms": round(total_ms / launches, 4), "launches": launches,
-                     "hbm_frac": round(f_hbm, 4), "alu_frac": round(f_alu, 4)})
+    roofline = kernel_roofline(times, KERNEL_ALGO, ncell, FP64_VECTOR_PEAK_TFLOPS)
     kernel_ms = {k: round(v[0] / args.steps, 4) for k, v in sorted(times.items())}
 
     out = {
@@ -247,6 +338,11 @@ def main():
     if not args.no_fp32:
         out["fp32_bulk"] = fp32_leg(n, state, warm_dts, dts, sim.state(device=True))
     sim.close()
+    if not args.no_dust:
+        out["dust"] = dust_leg(args.dust_n, args.side_steps, args.side_warmup, args.seed)
+    if not args.no_paper_config:
+        out["paper_config"] = paper_config_leg(tuple(args.paper_shape), args.side_steps,
+                                               args.side_warmup)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(n, state, args.cpu_seconds)

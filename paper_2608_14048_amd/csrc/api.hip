@@ -20,15 +20,16 @@ enum TimerSlot {
     T_MHD_CT_PRED,
     T_MHD_CT_CORR,
     T_CFL,
-    T_DUST_PRIMS,
-    T_DUST_FLUX,
-    T_IMEX_STAGE1,
-    T_IMEX_STAGE2,
+    T_DUST_PASS1,
+    T_DUST_PASS2,
+    T_DUST_DRAG1,
+    T_DUST_DRAG2,
     T_NSLOT
 };
 static const char* const kSlotNames[T_NSLOT] = {
     "mhd_flux_predictor", "mhd_flux_corrector", "mhd_ct_update_predictor",
-    "mhd_ct_update_corrector", "cfl", "dust_prims", "dust_flux", "imex_stage1", "imex_stage2"};
+    "mhd_ct_update_corrector", "cfl", "dust_fluid_pass_stage1", "dust_fluid_pass_stage2",
+    "dust_drag_stage1", "dust_drag_cfl_stage2"};
 
 struct EventTimer {
     int cap = 0, used = 0;
@@ -50,10 +51,10 @@ struct mhd_ctx {
     bool fp32;      // FP32-bulk form of the MHD path
     // workspace views
     void* reg[3];   // state registers (MHD rotates all three; see reg_view for the layout)
-    double* W;      // primitives (dust)
-    void* F;        // face fluxes, 3 direction blocks (the path's real type)
+    void* F;        // MHD face fluxes, 3 direction blocks (the path's real type)
     void* Rc;       // cell-centred E = -v x B (MHD)
     FusedGrid fg;   // tiling of the MHD stage kernels
+    DustGrid dg;    // tiling of the dust fluid passes
     double* partial;
     double* scalars;  // [0] dt of the current state, [1..] diagnostics
     int cur;        // register holding the current state
@@ -66,7 +67,7 @@ namespace {
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t reg, nreg, W, F, Rc, partial, scalars, total;
+    size_t reg, nreg, F, Rc, partial, scalars, total;
 };
 
 // z planes per workgroup of the MHD kernels: about 2048 workgroups on large grids.
@@ -141,16 +142,16 @@ Layout layout(const mhd_grid* g, const mhd_physics* p, const mhd_scheme* sc)
     Layout L;
     L.reg = is_mhd ? align256(register_bytes(n, fp32)) : align256(field * nv);
     L.nreg = is_mhd ? 3 : 2;
-    L.W = is_mhd ? 0 : align256(field * nv);
-    // for the FP32-bulk form the flux area also stages a canonical FP64 state (8 fields)
-    L.F = is_mhd ? align256(rfield * 21 > field * 8 ? rfield * 21 : field * 8) : align256(field * 3 * nv);
+    // for the FP32-bulk form the flux area also stages a canonical FP64 state (8 fields);
+    // the dust path keeps no arrays besides its two registers
+    L.F = is_mhd ? align256(rfield * 21 > field * 8 ? rfield * 21 : field * 8) : 0;
     L.Rc = is_mhd ? align256(rfield * 3) : 0;
     size_t nb = blocks_for(n);
     const size_t nf = fused_grid(make_geo(g), choose_kz(g)).nblk;
     if (nf > nb) nb = nf;
     L.partial = align256(nb * sizeof(double) * (size_t)diag_count(MHD_MAX_DUST));
     L.scalars = align256(sizeof(double) * 64);
-    L.total = L.nreg * L.reg + L.W + L.F + L.Rc + L.partial + L.scalars;
+    L.total = L.nreg * L.reg + L.F + L.Rc + L.partial + L.scalars;
     return L;
 }
 
@@ -191,14 +192,6 @@ mhd_status cfl_of(mhd_ctx* c, const double* U)
     Tick t(c, T_CFL);
     if (c->is_mhd) return dev(launch_cfl_mhd(c->geo, c->mp, U, c->partial, c->scalars, c->cfl_scale, c->stream));
     return dev(launch_cfl_dust(c->geo, c->dp, U, c->partial, c->scalars, c->cfl_scale, c->stream));
-}
-
-mhd_status refresh_cfl(mhd_ctx* c)
-{
-    hipError_t e;
-    const double* U = canonical_view(c, &e);
-    if (e != hipSuccess) return MHD_E_DEVICE;
-    return cfl_of(c, U);
 }
 
 // One stage: fluxes of `in`, then out = g0 in + g1 base + bdt L(in) (and, if last,
@@ -250,30 +243,29 @@ mhd_status step_mhd(mhd_ctx* c, double dt)
     return st;
 }
 
+// Both IMEX2P stages; stage 1 writes U1 = reg[1 - cur], stage 2 overwrites u = reg[cur]
+// and leaves the CFL step of the new state in scalars[0].
 mhd_status step_dust(mhd_ctx* c, double dt)
 {
     double* u = (double*)c->reg[c->cur];
     double* U1 = (double*)c->reg[1 - c->cur];
     const int recon = c->scheme.recon;
-    hipError_t e = hipSuccess;
-    for (int stage = 0; stage < 2 && e == hipSuccess; ++stage) {
-        const double* src = stage == 0 ? u : U1;
-        {
-            Tick t(c, T_DUST_PRIMS);
-            e = launch_dust_prims(c->geo, c->dp, src, c->W, c->stream);
-        }
-        if (e == hipSuccess) {
-            Tick t(c, T_DUST_FLUX);
-            e = launch_dust_fluxes(c->geo, c->dp, recon, c->W, (double*)c->F, c->stream);
-        }
-        if (e != hipSuccess) break;
-        if (stage == 0) {
-            Tick t(c, T_IMEX_STAGE1);
-            e = launch_imex_stage1(c->geo, c->dp, u, (const double*)c->F, U1, dt, c->stream);
-        } else {
-            Tick t(c, T_IMEX_STAGE2);
-            e = launch_imex_stage2(c->geo, c->dp, u, U1, (const double*)c->F, dt, c->stream);
-        }
+    hipError_t e;
+    {
+        Tick t(c, T_DUST_PASS1);
+        e = launch_fluid_pass1(c->geo, c->dp, c->dg, recon, u, U1, dt, c->stream);
+    }
+    if (e == hipSuccess) {
+        Tick t(c, T_DUST_DRAG1);
+        e = launch_drag1(c->geo, c->dp, U1, dt, c->stream);
+    }
+    if (e == hipSuccess) {
+        Tick t(c, T_DUST_PASS2);
+        e = launch_fluid_pass2(c->geo, c->dp, c->dg, recon, u, U1, dt, c->stream);
+    }
+    if (e == hipSuccess) {
+        Tick t(c, T_DUST_DRAG2);
+        e = launch_drag2_cfl(c->geo, c->dp, u, U1, dt, c->partial, c->scalars, c->cfl_scale, c->stream);
     }
     return dev(e);
 }
@@ -329,6 +321,7 @@ mhd_status mhd_create(const mhd_grid* grid, const mhd_physics* phys, const mhd_s
 
     c->geo = make_geo(grid);
     c->fg = fused_grid(c->geo, choose_kz(grid));
+    c->dg = dust_grid(c->geo, 1 + (phys->eos == MHD_EOS_ADIABATIC_MHD ? 0 : phys->ndust));
     c->mp.gamma = phys->gamma;
     c->mp.gm1inv = 1.0 / (phys->gamma - 1.0);
     c->mp.rho_floor = phys->rho_floor;
@@ -353,8 +346,7 @@ mhd_status mhd_create(const mhd_grid* grid, const mhd_physics* phys, const mhd_s
         c->reg[r] = r < L.nreg ? (void*)base : nullptr;
         if (r < L.nreg) base += L.reg;
     }
-    c->W = L.W ? (double*)base : nullptr; base += L.W;
-    c->F = (void*)base; base += L.F;
+    c->F = L.F ? (void*)base : nullptr; base += L.F;
     c->Rc = L.Rc ? (void*)base : nullptr; base += L.Rc;
     c->partial = (double*)base; base += L.partial;
     c->scalars = (double*)base;
@@ -416,10 +408,8 @@ mhd_status mhd_step(mhd_ctx* c, double dt)
 {
     if (!c) return MHD_E_INVAL;
     if (!(dt > 0.0) || !std::isfinite(dt)) return MHD_E_INVAL;
-    if (c->is_mhd) return step_mhd(c, dt);  // the last stage reduces the CFL step itself
-    mhd_status st = step_dust(c, dt);
-    if (st != MHD_OK) return st;
-    return refresh_cfl(c);
+    // the last stage of either path reduces the CFL step of the new state itself
+    return c->is_mhd ? step_mhd(c, dt) : step_dust(c, dt);
 }
 
 mhd_status mhd_dt_cfl(mhd_ctx* c, double* dt)

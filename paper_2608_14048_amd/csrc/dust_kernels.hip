@@ -15,6 +15,21 @@
 //   v_g' = (p_g + sum_k w_k p_k) / (rho_g + sum_k w_k rho_k),
 //   p_k' = (t_k p_k + h rho_k v_g') / (t_k + h),   p_g' = rho_g v_g',
 // exact, O(N) and momentum conserving.
+//
+// Each stage is two launches:
+//   k_fluid_pass  one workgroup = one fluid on a 64 x 4 tile of xy columns marching a
+//                 chunk of z planes.  The fluid's primitives of the current plane and
+//                 its x/y halo are staged in LDS (double buffered: the loads of plane
+//                 k+1 are issued before plane k is computed), the z stencil of each
+//                 column is a register pipeline that carries the flux of the low z
+//                 face.  Every cell solves the Riemann problems on both of its x and y
+//                 faces (no flux array, no extra barrier) and writes the explicit part
+//                 of its stage:
+//                   stage 1: X = u + h L(u);  stage 2: X = cu u + c1 U1 + cf L(U1).
+//                 Densities are final after this pass (drag moves only momentum).
+//   k_drag        pointwise: adds the stage-1 drag rates (stage 2), solves S_h for the
+//                 momenta in place and, after stage 2, reduces the CFL step of the new
+//                 state (one partial per workgroup).
 #include "launch.hpp"
 #include "physics.hpp"
 
@@ -23,236 +38,528 @@ namespace mhd {
 namespace {
 constexpr double kLam = 1.7071067811865475244;    // 1 + 1/sqrt(2)
 constexpr double kDelta = 0.70710678118654752440;  // 1 - 1/(2 lam) = 1/sqrt(2)
+
+constexpr int DTX = 64;  // lanes along x
+constexpr int DTY = 4;   // waves along y
+
+// Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous run of work
+// items so neighbouring tiles of one fluid share an L2.
+__device__ __forceinline__ unsigned int xcd_item(unsigned int b, unsigned int nb)
+{
+    const unsigned int q = nb >> 3, rem = nb & 7u;
+    const unsigned int x = b & 7u, r = b >> 3;
+    return x * q + (x < rem ? x : rem) + r;
 }
 
-// Primitives of fluid s at cell c: gas density floor; dust below its floor reads as
-// the floor at rest.
-__device__ __forceinline__ void fluid_prim(const DustParams& p, int s, const double* __restrict__ U,
-                                           long long n, long long c, double w[4])
+__device__ __forceinline__ int wrap_any(int i, int n)
 {
-    const double* u = U + 4LL * s * n;
-    double d = u[c];
-    if (s == 0) {
-        if (d < p.rho_floor) d = p.rho_floor;
-    } else if (d < p.dust_floor) {
-        w[0] = p.dust_floor;
-        w[1] = w[2] = w[3] = 0.0;
-        return;
+    if (i >= 0 && i < n) return i;
+    const int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ double ld(const double* __restrict__ base, unsigned int idx)
+{
+    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + idx * 8u);
+}
+__device__ __forceinline__ void st(double* base, unsigned int idx, double v)
+{
+    *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + idx * 8u) = v;
+}
+
+// a / b for finite b != 0: the hardware reciprocal refined by one Newton step, then one
+// residual correction of the quotient (within an ulp of the IEEE quotient for normal
+// operands; six instructions instead of the scaled IEEE sequence).
+__device__ __forceinline__ double div_nr(double a, double b)
+{
+    double r = __builtin_amdgcn_rcp(b);
+    r = fma(fma(-b, r, 1.0), r, r);
+    const double q = a * r;
+    return fma(fma(-b, q, a), r, q);
+}
+
+// van Leer's harmonic-mean slope (the same formula as the shared helper, with div_nr:
+// the denominator is a sum of two numbers of one sign, never zero here).
+__device__ __forceinline__ double slope_hm(double am, double a0, double ap)
+{
+    const double dm = a0 - am, dp = ap - a0;
+    const double pr = dm * dp;
+    return pr > 0.0 ? div_nr(2.0 * pr, dm + dp) : 0.0;
+}
+
+// Halo (cells on each side) of the reconstruction when both faces of a cell are built.
+template <int RECON>
+struct Halo {
+    static constexpr int H = RECON == 0 ? 1 : 2;
+};
+
+// States on the low face (lo) and high face (hi) of the middle cell of a[0..2H]:
+// donor cell or van Leer-limited PLM, the same formula on every face.
+template <int RECON>
+__device__ __forceinline__ void both_faces(const double* a, double& loL, double& loR, double& hiL,
+                                           double& hiR)
+{
+    if constexpr (RECON == 0) {
+        loL = a[0]; loR = a[1]; hiL = a[1]; hiR = a[2];
+    } else {
+        const double sm = slope_hm(a[0], a[1], a[2]);
+        const double s0 = slope_hm(a[1], a[2], a[3]);
+        const double sp = slope_hm(a[2], a[3], a[4]);
+        loL = a[1] + 0.5 * sm;
+        loR = a[2] - 0.5 * s0;
+        hiL = a[2] + 0.5 * s0;
+        hiR = a[3] - 0.5 * sp;
     }
-    w[0] = d;
-    w[1] = u[n + c] / d;
-    w[2] = u[2 * n + c] / d;
-    w[3] = u[3 * n + c] / d;
 }
 
-__global__ __launch_bounds__(kBlock) void k_dust_prims(Geo g, DustParams p, const double* __restrict__ U,
-                                                       double* __restrict__ W)
+// Face flux along direction D from the global-frame states; returns global-frame
+// components (mass, Mx, My, Mz).
+template <int D>
+__device__ __forceinline__ void face_flux(bool gas, double cs, const double L[4], const double R[4],
+                                          double out[4])
 {
-    const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= g.n) return;
-    const long long n = g.n;
-    for (int s = 0; s <= p.nd; ++s) {
-        double w[4];
-        fluid_prim(p, s, U, n, c, w);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) W[(4LL * s + q) * n + c] = w[q];
-    }
-}
-
-// Face fluxes of every fluid on the left face of each cell along D; F holds
-// 4(1+nd) fields in the global frame (mass, Mx, My, Mz per fluid).
-template <int D, int RECON>
-__global__ __launch_bounds__(kBlock) void k_dust_flux(Geo g, DustParams p, const double* __restrict__ W,
-                                                      double* __restrict__ F)
-{
-    const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= g.n) return;
-    int i, j, k;
-    cell_ijk(g, c, i, j, k);
     constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+    const Prim4 l{L[0], L[1 + D], L[1 + T1], L[1 + T2]};
+    const Prim4 r{R[0], R[1 + D], R[1 + T1], R[1 + T2]};
+    Flux4 f;
+    if (gas)
+        riemann_iso_hlle(l, r, cs, f);
+    else
+        riemann_dust(l, r, f);
+    out[0] = f.d;
+    out[1 + D] = f.mn;
+    out[1 + T1] = f.mt1;
+    out[1 + T2] = f.mt2;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------------
+// explicit part of a stage, one fluid per workgroup
+// ----------------------------------------------------------------------------------
+
+struct PassArgs {
+    const double* src;   // state whose fluxes are taken (u in stage 1, U1 in stage 2)
+    const double* base;  // stage 2: u (read at the own cell only); stage 1: unused
+    double* out;         // stage 1: U1; stage 2: u (in place: each cell reads then writes itself)
+    double h;            // stage 1: lam dt; stage 2: (1 - delta) dt
+    double cu, c1;       // stage 2 weights of u and U1
+};
+
+// z reconstruction of one variable of one column as a pipeline over the planes the
+// column visits: push(plane m + 1 + AHEAD) returns the two states on the face m + 1/2
+// (one slope per plane for PLM).
+template <int RECON>
+struct ZLine;
+template <>
+struct ZLine<0> {
+    static constexpr int AHEAD = 0, PRIME = 1;
+    double prev;
+    __device__ void prime(const double* a) { prev = a[0]; }
+    __device__ void push(double a, double& aL, double& aR)
+    {
+        aL = prev;
+        aR = a;
+        prev = a;
+    }
+};
+template <>
+struct ZLine<1> {
+    static constexpr int AHEAD = 1, PRIME = 3;
+    double am, a0, apl;  // a(m-1), a(m), high-side state of cell m-1
+    __device__ void prime(const double* a)
+    {
+        apl = a[1] + 0.5 * slope_hm(a[0], a[1], a[2]);
+        am = a[1];
+        a0 = a[2];
+    }
+    __device__ void push(double a, double& aL, double& aR)
+    {
+        const double d = slope_hm(am, a0, a);
+        aL = apl;
+        aR = a0 - 0.5 * d;
+        apl = a0 + 0.5 * d;
+        am = a0;
+        a0 = a;
+    }
+};
+
+template <int RECON, int STAGE>
+__global__ __launch_bounds__(DTX* DTY) void k_fluid_pass(Geo g, DustParams p, PassArgs a, int kz,
+                                                           unsigned int ntx, unsigned int nty,
+                                                           unsigned int ntiles, unsigned int nblk)
+{
+    constexpr int H = Halo<RECON>::H, W = 2 * H + 1;
+    constexpr int LX = DTX + 2 * H, LY = DTY + 2 * H;
+    constexpr int NT = DTX * DTY, NI = (LX * LY + NT - 1) / NT;  // staging items per thread
+    using Z = ZLine<RECON>;
+    __shared__ double sw[2][4][LY][LX];  // primitives of plane k (and k+1 being staged)
+
+    const unsigned int item = xcd_item(blockIdx.x, nblk);
+    const int s = (int)(item / ntiles);  // fluid: 0 gas, 1.. dust
+    const unsigned int t = item - (unsigned int)s * ntiles;
+    const bool gas = s == 0;
+    const int x0 = (int)(t % ntx) * DTX;
+    const int y0 = (int)((t / ntx) % nty) * DTY;
+    const int k0 = (int)(t / (ntx * nty)) * kz;
+    const int k1 = min(k0 + kz, g.nz);
+    const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
+    const int i = x0 + lane, j = y0 + row;
+    const bool live = i < g.nx && j < g.ny;
+    const int ic = live ? i : 0, jc = live ? j : 0;
     const long long n = g.n;
-    long long at[6];
+    const unsigned int plane = (unsigned int)g.nx * (unsigned int)g.ny;
+    const double* f[4];
+    double* o[4];
 #pragma unroll
-    for (int s = 0; s < 6; ++s) at[s] = shifted(g, i, j, k, D, s - 3);
-    for (int s = 0; s <= p.nd; ++s) {
-        const double* w = W + 4LL * s * n;
-        double st[6];
-        Prim4 L, R;
+    for (int q = 0; q < 4; ++q) {
+        f[q] = a.src + (4LL * s + q) * n;
+        o[q] = a.out + (4LL * s + q) * n;
+    }
+    const double* b0 = a.base + 4LL * s * n;
+    const double cs = p.cs;
+    const unsigned int col = (unsigned int)jc * g.nx + ic;
+
+    // this thread's staging items of a plane (tile + x/y halo, corners skipped)
+    unsigned int soff[NI];
+    int sr[NI], sc[NI];
+    bool sv[NI];
 #pragma unroll
-        for (int m = 0; m < 6; ++m) st[m] = w[at[m]];
-        face_states<RECON>(st, L.d, R.d);
+    for (int m = 0; m < NI; ++m) {
+        const int q = threadIdx.x + m * NT;
+        sr[m] = q / LX;
+        sc[m] = q - sr[m] * LX;
+        const bool xh = sc[m] < H || sc[m] >= H + DTX, yh = sr[m] < H || sr[m] >= H + DTY;
+        sv[m] = q < LX * LY && !(xh && yh);
+        const int gx = wrap_any(x0 + sc[m] - H, g.nx), gy = wrap_any(y0 + sr[m] - H, g.ny);
+        soff[m] = sv[m] ? (unsigned int)gy * g.nx + gx : 0u;
+    }
+    // primitives from the raw state: the gas density is floored; a dust species below
+    // its floor reads as the floor at rest
+    auto prim_of = [&](const double raw[4], double w[4]) {
+        const bool rest = !gas && raw[0] < p.dust_floor;
+        double d = raw[0];
+        if (gas && d < p.rho_floor) d = p.rho_floor;
+        const double id = 1.0 / d;
+        w[0] = rest ? p.dust_floor : d;
+        w[1] = rest ? 0.0 : raw[1] * id;
+        w[2] = rest ? 0.0 : raw[2] * id;
+        w[3] = rest ? 0.0 : raw[3] * id;
+    };
+    auto load_raw = [&](unsigned int c, double raw[4]) {
 #pragma unroll
-        for (int m = 0; m < 6; ++m) st[m] = w[(1 + D) * n + at[m]];
-        face_states<RECON>(st, L.vn, R.vn);
+        for (int q = 0; q < 4; ++q) raw[q] = ld(f[q], c);
+    };
+    double raw[NI][4];
+    auto fetch_plane = [&](int kk) {
+        const unsigned int pb = (unsigned int)kk * plane;
 #pragma unroll
-        for (int m = 0; m < 6; ++m) st[m] = w[(1 + T1) * n + at[m]];
-        face_states<RECON>(st, L.vt1, R.vt1);
+        for (int m = 0; m < NI; ++m)
+            if (sv[m]) load_raw(pb + soff[m], raw[m]);
+    };
+    auto store_plane = [&](int buf) {
 #pragma unroll
-        for (int m = 0; m < 6; ++m) st[m] = w[(1 + T2) * n + at[m]];
-        face_states<RECON>(st, L.vt2, R.vt2);
-        Flux4 f;
-        if (s == 0)
-            riemann_iso_hlle(L, R, p.cs, f);
-        else
-            riemann_dust(L, R, f);
-        double* o = F + 4LL * s * n;
-        o[c] = f.d;
-        o[(1 + D) * n + c] = f.mn;
-        o[(1 + T1) * n + c] = f.mt1;
-        o[(1 + T2) * n + c] = f.mt2;
+        for (int m = 0; m < NI; ++m)
+            if (sv[m]) {
+                double w[4];
+                prim_of(raw[m], w);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) sw[buf][v][sr[m]][sc[m]] = w[v];
+            }
+    };
+
+    // z pipeline of the own column, primed so that the first push yields face k0 - 1/2
+    Z zl[4];
+    {
+        double pre[4][Z::PRIME];
+#pragma unroll
+        for (int m = 0; m < Z::PRIME; ++m) {
+            double r4[4], w[4];
+            load_raw((unsigned int)wrap_any(k0 - Z::PRIME + Z::AHEAD + m, g.nz) * plane + col, r4);
+            prim_of(r4, w);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) pre[v][m] = w[v];
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) zl[v].prime(pre[v]);
+    }
+    double zraw[4];  // raw state of the next plane the z pipeline takes
+    load_raw((unsigned int)wrap_any(k0 + Z::AHEAD, g.nz) * plane + col, zraw);
+    double fzlo[4];  // z flux on the low face of the current cell
+    {
+        double w[4], L[4], R[4];
+        prim_of(zraw, w);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) zl[v].push(w[v], L[v], R[v]);
+        face_flux<2>(gas, cs, L, R, fzlo);
+    }
+    load_raw((unsigned int)wrap_any(k0 + 1 + Z::AHEAD, g.nz) * plane + col, zraw);
+    fetch_plane(k0);
+    store_plane(k0 & 1);
+    __syncthreads();
+
+    for (int k = k0; k < k1; ++k) {
+        const int cur = k & 1;
+        // loads for the next plane go out first; they land while this plane computes
+        const bool more = k + 1 < k1;
+        if (more) fetch_plane(k + 1);
+        const unsigned int c = (unsigned int)k * plane + col;
+        double own[4], ub[4];
+        load_raw(c, own);
+        if constexpr (STAGE == 2) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) ub[v] = ld(b0 + v * n, c);
+        }
+        double zw[4];
+        prim_of(zraw, zw);
+        if (more) load_raw((unsigned int)wrap_any(k + 2 + Z::AHEAD, g.nz) * plane + col, zraw);
+
+        // acc = ((fx + fy) + fz): flux differences accumulated direction by direction
+        double acc[4];
+        {
+            double Lm[4], Rm[4], Lp[4], Rp[4], st5[W], fl[4], fh[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+#pragma unroll
+                for (int m = 0; m < W; ++m) st5[m] = sw[cur][v][row + H][lane + m];
+                both_faces<RECON>(st5, Lm[v], Rm[v], Lp[v], Rp[v]);
+            }
+            face_flux<0>(gas, cs, Lm, Rm, fl);
+            face_flux<0>(gas, cs, Lp, Rp, fh);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] = (fh[v] - fl[v]) * g.inv_dx[0];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+#pragma unroll
+                for (int m = 0; m < W; ++m) st5[m] = sw[cur][v][row + m][lane + H];
+                both_faces<RECON>(st5, Lm[v], Rm[v], Lp[v], Rp[v]);
+            }
+            face_flux<1>(gas, cs, Lm, Rm, fl);
+            face_flux<1>(gas, cs, Lp, Rp, fh);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] = acc[v] + (fh[v] - fl[v]) * g.inv_dx[1];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) zl[v].push(zw[v], Lp[v], Rp[v]);
+            face_flux<2>(gas, cs, Lp, Rp, fh);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                acc[v] = acc[v] + (fh[v] - fzlo[v]) * g.inv_dx[2];
+                fzlo[v] = fh[v];
+            }
+        }
+        if (live) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double L = -acc[v];
+                // the gas acceleration acts on the raw gas density
+                if (gas && v > 0) L += own[0] * p.gacc[v - 1];
+                double X;
+                if constexpr (STAGE == 1)
+                    X = own[v] + a.h * L;
+                else
+                    X = (a.cu * ub[v] + a.c1 * own[v]) + a.h * L;
+                st(o[v], c, X);
+            }
+        }
+        if (more) store_plane(cur ^ 1);
+        __syncthreads();
     }
 }
 
-// -flux divergence of variable v at cell c (F: 3 direction blocks of nv fields).
-__device__ __forceinline__ double neg_div(const Geo& g, const double* __restrict__ F, long long nv,
-                                          int v, long long c, long long cx, long long cy, long long cz)
-{
-    const long long n = g.n;
-    const double* Fx = F;
-    const double* Fy = F + nv * n;
-    const double* Fz = F + 2 * nv * n;
-    const double fx = (Fx[v * n + cx] - Fx[v * n + c]) * g.inv_dx[0];
-    const double fy = (Fy[v * n + cy] - Fy[v * n + c]) * g.inv_dx[1];
-    const double fz = (Fz[v * n + cz] - Fz[v * n + c]) * g.inv_dx[2];
-    return -((fx + fy) + fz);
-}
+// ----------------------------------------------------------------------------------
+// drag solve (and the CFL step after stage 2), pointwise
+// ----------------------------------------------------------------------------------
 
-// Closed-form drag solve of one momentum component, in place on p[0..nd].
+// Closed-form drag solve of one momentum component, in place on mom[0..ND].
+template <int ND>
 __device__ __forceinline__ void drag_solve(const DustParams& p, const double* rho, double* mom,
                                            double h)
 {
     double num = mom[0], den = rho[0];
-    for (int s = 1; s <= p.nd; ++s) {
+#pragma unroll
+    for (int s = 1; s <= ND; ++s) {
         const double w = h / (p.ts[s - 1] + h);
         num += w * mom[s];
         den += w * rho[s];
     }
     const double vg = num / den;
-    for (int s = 1; s <= p.nd; ++s) {
+#pragma unroll
+    for (int s = 1; s <= ND; ++s) {
         const double t = p.ts[s - 1];
         mom[s] = (t * mom[s] + h * rho[s] * vg) / (t + h);
     }
     mom[0] = rho[0] * vg;
 }
 
-__global__ __launch_bounds__(kBlock) void k_imex_stage1(Geo g, DustParams p, const double* __restrict__ u,
-                                                        const double* __restrict__ F,
-                                                        double* __restrict__ U1, double dt)
+// Velocity component a of fluid s at cell c of state U (the primitive recovery of the
+// explicit part).
+__device__ __forceinline__ double fluid_vel(const DustParams& p, const double* __restrict__ U,
+                                            long long n, int s, int a, unsigned int c)
 {
-    const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= g.n) return;
-    int i, j, k;
-    cell_ijk(g, c, i, j, k);
-    const long long n = g.n;
-    const long long nv = 4LL * (p.nd + 1);
-    const long long cx = shifted(g, i, j, k, 0, 1), cy = shifted(g, i, j, k, 1, 1),
-                    cz = shifted(g, i, j, k, 2, 1);
-    const double h = kLam * dt;
-    double rho[kMaxDust + 1];
-    for (int s = 0; s <= p.nd; ++s) {
-        const int v = 4 * s;
-        rho[s] = u[v * n + c] + h * neg_div(g, F, nv, v, c, cx, cy, cz);
-        U1[v * n + c] = rho[s];
+    const double* u = U + 4LL * s * n;
+    double d = ld(u, c);
+    if (s == 0) {
+        if (d < p.rho_floor) d = p.rho_floor;
+    } else if (d < p.dust_floor) {
+        return 0.0;
     }
-    const double rg = u[c];
-    for (int a = 0; a < 3; ++a) {
-        double mom[kMaxDust + 1];
-        for (int s = 0; s <= p.nd; ++s) {
-            const int v = 4 * s + 1 + a;
-            double L = neg_div(g, F, nv, v, c, cx, cy, cz);
-            if (s == 0) L += rg * p.gacc[a];
-            mom[s] = u[v * n + c] + h * L;
+    return ld(u + (1 + a) * n, c) / d;
+}
+
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min_nan(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// X: the explicit part (densities final); U1: stage-1 state (stage 2 only).  The number
+// of dust species ND is a template parameter so the per-cell vectors live in registers.
+template <int STAGE, int ND>
+__global__ __launch_bounds__(kBlock) void k_drag(Geo g, DustParams p, double* __restrict__ X,
+                                                 const double* __restrict__ U1, double h, double cg,
+                                                 double* __restrict__ partial)
+{
+    const long long cl = (long long)blockIdx.x * kBlock + threadIdx.x;
+    const long long n = g.n;
+    double r = INFINITY;
+    if (cl < n) {
+        const unsigned int c = (unsigned int)cl;
+        double rho[ND + 1];
+#pragma unroll
+        for (int s = 0; s <= ND; ++s) rho[s] = ld(X + 4LL * s * n, c);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double mom[ND + 1];
+#pragma unroll
+            for (int s = 0; s <= ND; ++s) mom[s] = ld(X + (4LL * s + 1 + a) * n, c);
+            if constexpr (STAGE == 2) {
+                // + (1 - lam - delta) dt G(U1): drag rates of the stage-1 state
+                const double vg = fluid_vel(p, U1, n, 0, a, c);
+                double gsum = 0.0;
+#pragma unroll
+                for (int s = 1; s <= ND; ++s) {
+                    const double fk = ld(U1 + 4LL * s * n, c) * (vg - fluid_vel(p, U1, n, s, a, c)) / p.ts[s - 1];
+                    mom[s] = mom[s] + cg * fk;
+                    gsum -= fk;
+                }
+                mom[0] = mom[0] + cg * gsum;
+            }
+            drag_solve<ND>(p, rho, mom, h);
+#pragma unroll
+            for (int s = 0; s <= ND; ++s) st(X + (4LL * s + 1 + a) * n, c, mom[s]);
+            if constexpr (STAGE == 2) {
+                // time step of the new state, as the standalone CFL kernel takes it
+#pragma unroll
+                for (int s = 0; s <= ND; ++s) {
+                    double d = rho[s], v;
+                    if (s == 0) {
+                        if (d < p.rho_floor) d = p.rho_floor;
+                        v = mom[s] / d;
+                    } else {
+                        v = d < p.dust_floor ? 0.0 : mom[s] / d;
+                    }
+                    const double cs = s == 0 ? p.cs : 0.0;
+                    r = min_nan(r, g.dx[a] / (fabs(v) + cs));
+                }
+            }
         }
-        drag_solve(p, rho, mom, h);
-        for (int s = 0; s <= p.nd; ++s) U1[(4 * s + 1 + a) * n + c] = mom[s];
+    }
+    if constexpr (STAGE == 2) {
+        __shared__ double sm[kBlock / 64];
+        r = wave_min(r);
+        if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = r;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double m = sm[0];
+#pragma unroll
+            for (int w = 1; w < kBlock / 64; ++w) m = min_nan(m, sm[w]);
+            partial[blockIdx.x] = m;
+        }
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_imex_stage2(Geo g, DustParams p, double* __restrict__ u,
-                                                        const double* __restrict__ U1,
-                                                        const double* __restrict__ F, double dt)
+template <int STAGE, int ND>
+static void drag_launch(const Geo& g, const DustParams& p, double* X, const double* U1, double h,
+                        double cg, double* partial, hipStream_t s)
 {
-    const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
-    if (c >= g.n) return;
-    int i, j, k;
-    cell_ijk(g, c, i, j, k);
-    const long long n = g.n;
-    const long long nv = 4LL * (p.nd + 1);
-    const long long cx = shifted(g, i, j, k, 0, 1), cy = shifted(g, i, j, k, 1, 1),
-                    cz = shifted(g, i, j, k, 2, 1);
-    const double h = kLam * dt;
-    const double cu = 1.0 - kDelta / kLam, c1 = kDelta / kLam;
-    const double cf = (1.0 - kDelta) * dt, cg = (1.0 - kLam - kDelta) * dt;
-    double rho[kMaxDust + 1];
-    for (int s = 0; s <= p.nd; ++s) {
-        const int v = 4 * s;
-        rho[s] = (cu * u[v * n + c] + c1 * U1[v * n + c]) + cf * neg_div(g, F, nv, v, c, cx, cy, cz);
-    }
-    // drag rates of the stage-1 state: velocities through the same primitive recovery
-    double wg[4];
-    fluid_prim(p, 0, U1, n, c, wg);
-    const double rg1 = U1[c];
-    for (int a = 0; a < 3; ++a) {
-        double mom[kMaxDust + 1];
-        double gsum = 0.0;
-        for (int s = 1; s <= p.nd; ++s) {
-            double wd[4];
-            fluid_prim(p, s, U1, n, c, wd);
-            const double fk = U1[4LL * s * n + c] * (wg[1 + a] - wd[1 + a]) / p.ts[s - 1];
-            const int v = 4 * s + 1 + a;
-            const double L = neg_div(g, F, nv, v, c, cx, cy, cz);
-            mom[s] = ((cu * u[v * n + c] + c1 * U1[v * n + c]) + cf * L) + cg * fk;
-            gsum -= fk;
+    hipLaunchKernelGGL((k_drag<STAGE, ND>), dim3(blocks_for(g.n)), dim3(kBlock), 0, s, g, p, X, U1, h,
+                       cg, partial);
+}
+
+// Dispatch on the species count (1..kMaxDust) to the specialised kernel.
+template <int STAGE, int ND = 1>
+static hipError_t drag_dispatch(const Geo& g, const DustParams& p, double* X, const double* U1, double h,
+                                double cg, double* partial, hipStream_t s)
+{
+    if constexpr (ND > kMaxDust) {
+        return hipErrorInvalidValue;
+    } else {
+        if (p.nd == ND) {
+            drag_launch<STAGE, ND>(g, p, X, U1, h, cg, partial, s);
+            return hipGetLastError();
         }
-        const int v0 = 1 + a;
-        const double L0 = neg_div(g, F, nv, v0, c, cx, cy, cz) + rg1 * p.gacc[a];
-        mom[0] = ((cu * u[v0 * n + c] + c1 * U1[v0 * n + c]) + cf * L0) + cg * gsum;
-        drag_solve(p, rho, mom, h);
-        for (int s = 0; s <= p.nd; ++s) u[(4 * s + 1 + a) * n + c] = mom[s];
+        return drag_dispatch<STAGE, ND + 1>(g, p, X, U1, h, cg, partial, s);
     }
-    for (int s = 0; s <= p.nd; ++s) u[4LL * s * n + c] = rho[s];
 }
 
 // ----------------------------------------------------------------------------------
 
-hipError_t launch_dust_prims(const Geo& g, const DustParams& p, const double* U, double* W,
-                             hipStream_t s)
+DustGrid dust_grid(const Geo& g, int nfluids)
 {
-    hipLaunchKernelGGL(k_dust_prims, dim3(blocks_for(g.n)), dim3(kBlock), 0, s, g, p, U, W);
-    return hipGetLastError();
+    DustGrid d;
+    d.ntx = (unsigned int)((g.nx + DTX - 1) / DTX);
+    d.nty = (unsigned int)((g.ny + DTY - 1) / DTY);
+    const long long tiles = (long long)d.ntx * d.nty * nfluids;
+    // about 4096 workgroups, at least 8 planes each (the z window is primed per chunk)
+    const long long want = (4096 + tiles - 1) / tiles;
+    int kz = (int)((g.nz + want - 1) / want);
+    if (kz < 8) kz = 8;
+    if (kz > g.nz) kz = g.nz;
+    d.kz = kz;
+    d.ntz = (unsigned int)((g.nz + kz - 1) / kz);
+    d.ntiles = d.ntx * d.nty * d.ntz;
+    d.nblk = d.ntiles * (unsigned int)nfluids;
+    return d;
 }
 
 template <int RECON>
-static hipError_t dust_flux_all(const Geo& g, const DustParams& p, const double* W, double* F,
-                                hipStream_t s)
+static hipError_t pass(const Geo& g, const DustParams& p, const DustGrid& d, int stage, const PassArgs& a,
+                       hipStream_t s)
 {
-    const long long nvn = 4LL * (p.nd + 1) * g.n;
-    const dim3 gr(blocks_for(g.n)), bl(kBlock);
-    hipLaunchKernelGGL((k_dust_flux<0, RECON>), gr, bl, 0, s, g, p, W, F);
-    hipLaunchKernelGGL((k_dust_flux<1, RECON>), gr, bl, 0, s, g, p, W, F + nvn);
-    hipLaunchKernelGGL((k_dust_flux<2, RECON>), gr, bl, 0, s, g, p, W, F + 2 * nvn);
+    const dim3 gr(d.nblk), bl(DTX * DTY);
+    if (stage == 1)
+        hipLaunchKernelGGL((k_fluid_pass<RECON, 1>), gr, bl, 0, s, g, p, a, d.kz, d.ntx, d.nty, d.ntiles, d.nblk);
+    else
+        hipLaunchKernelGGL((k_fluid_pass<RECON, 2>), gr, bl, 0, s, g, p, a, d.kz, d.ntx, d.nty, d.ntiles, d.nblk);
     return hipGetLastError();
 }
 
-hipError_t launch_dust_fluxes(const Geo& g, const DustParams& p, int recon, const double* W,
-                              double* F, hipStream_t s)
+hipError_t launch_fluid_pass1(const Geo& g, const DustParams& p, const DustGrid& d, int recon,
+                              const double* u, double* U1, double dt, hipStream_t s)
 {
-    if (recon == 0) return dust_flux_all<0>(g, p, W, F, s);
-    return dust_flux_all<1>(g, p, W, F, s);
+    PassArgs a{u, nullptr, U1, kLam * dt, 0.0, 0.0};
+    return recon == 0 ? pass<0>(g, p, d, 1, a, s) : pass<1>(g, p, d, 1, a, s);
 }
 
-hipError_t launch_imex_stage1(const Geo& g, const DustParams& p, const double* u,
-                              const double* F, double* U1, double dt, hipStream_t s)
+hipError_t launch_fluid_pass2(const Geo& g, const DustParams& p, const DustGrid& d, int recon,
+                              double* u, const double* U1, double dt, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_imex_stage1, dim3(blocks_for(g.n)), dim3(kBlock), 0, s, g, p, u, F, U1, dt);
-    return hipGetLastError();
+    PassArgs a{U1, u, u, (1.0 - kDelta) * dt, 1.0 - kDelta / kLam, kDelta / kLam};
+    return recon == 0 ? pass<0>(g, p, d, 2, a, s) : pass<1>(g, p, d, 2, a, s);
 }
 
-hipError_t launch_imex_stage2(const Geo& g, const DustParams& p, double* u, const double* U1,
-                              const double* F, double dt, hipStream_t s)
+hipError_t launch_drag1(const Geo& g, const DustParams& p, double* U1, double dt, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_imex_stage2, dim3(blocks_for(g.n)), dim3(kBlock), 0, s, g, p, u, U1, F, dt);
-    return hipGetLastError();
+    return drag_dispatch<1>(g, p, U1, nullptr, kLam * dt, 0.0, nullptr, s);
+}
+
+hipError_t launch_drag2_cfl(const Geo& g, const DustParams& p, double* u, const double* U1, double dt,
+                            double* partial, double* dt_out, double cfl_scale, hipStream_t s)
+{
+    hipError_t e = drag_dispatch<2>(g, p, u, U1, kLam * dt, (1.0 - kLam - kDelta) * dt, partial, s);
+    if (e != hipSuccess) return e;
+    return launch_min_final(partial, blocks_for(g.n), cfl_scale, dt_out, s);
 }
 
 }  // namespace mhd

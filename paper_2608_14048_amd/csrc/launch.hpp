@@ -91,15 +91,23 @@ hipError_t launch_diag(const Geo& g, int mhd, int ndust, const double* U, double
                        double* out, hipStream_t s);
 
 // ---- isothermal gas + dust (IMEX2P) ----
-hipError_t launch_dust_prims(const Geo& g, const DustParams& p, const double* U, double* W,
-                             hipStream_t s);
-hipError_t launch_dust_fluxes(const Geo& g, const DustParams& p, int recon, const double* W,
-                              double* F, hipStream_t s);
-// stage 1: U1 = S_h(u + lam dt F(u)); stage 2: u <- S_h(RHS2) in place.
-hipError_t launch_imex_stage1(const Geo& g, const DustParams& p, const double* u,
-                              const double* F, double* U1, double dt, hipStream_t s);
-hipError_t launch_imex_stage2(const Geo& g, const DustParams& p, double* u, const double* U1,
-                              const double* F, double dt, hipStream_t s);
+// Tiling of the fluid passes: one workgroup per (fluid, 64 x 8 tile, chunk of kz planes).
+struct DustGrid {
+    int kz;
+    unsigned int ntx, nty, ntz, ntiles, nblk;
+};
+DustGrid dust_grid(const Geo& g, int nfluids);
+// Explicit parts: stage 1 writes X = u + lam dt L(u) into U1; stage 2 writes
+// X = cu u + c1 U1 + (1 - delta) dt L(U1) over u in place.
+hipError_t launch_fluid_pass1(const Geo& g, const DustParams& p, const DustGrid& d, int recon,
+                              const double* u, double* U1, double dt, hipStream_t s);
+hipError_t launch_fluid_pass2(const Geo& g, const DustParams& p, const DustGrid& d, int recon,
+                              double* u, const double* U1, double dt, hipStream_t s);
+// Drag solves in place on the explicit part; stage 2 adds the stage-1 drag rates first
+// and reduces the CFL step of the new state into dt_out (partial: ceil(n/kBlock) doubles).
+hipError_t launch_drag1(const Geo& g, const DustParams& p, double* U1, double dt, hipStream_t s);
+hipError_t launch_drag2_cfl(const Geo& g, const DustParams& p, double* u, const double* U1, double dt,
+                            double* partial, double* dt_out, double cfl_scale, hipStream_t s);
 
 inline unsigned int blocks_for(long long n) { return (unsigned int)((n + kBlock - 1) / kBlock); }
 

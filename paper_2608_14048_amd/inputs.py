@@ -132,20 +132,41 @@ def fast_eigenmode(rho=1.0, p=None, b0=(1.0, math.sqrt(2.0), 0.5), gamma=5.0 / 3
     return float(vals[i].real), r / r[0]
 
 
+def box_wave_frame(length):
+    """Wave frame of the oblique wave with one wavelength across each side of a box:
+    k = 2 pi (1/Lx, 1/Ly, 1/Lz), e1 = k/|k|, e2 = z^ x e1 normalised, e3 = e1 x e2."""
+    kvec = 2.0 * math.pi / np.asarray(length, dtype=np.float64)
+    e1 = kvec / np.linalg.norm(kvec)
+    e2 = np.array([-e1[1], e1[0], 0.0])
+    e2 /= np.linalg.norm(e2)
+    return kvec, (e1, e2, np.cross(e1, e2))
+
+
 def linear_wave(n=32, amp=1e-6, gamma=5.0 / 3.0, b0=(1.0, math.sqrt(2.0), 0.5), t=0.0,
-                along="diagonal"):
-    """Fast wave of amplitude amp on [0,1]^3 with k = 2 pi (1,1,1) (along="diagonal",
-    period (1/sqrt 3)/c_f) or k = 2 pi x^ on an n x 1 x 1 grid (along="x"); at time t
-    the exact linear solution.  Returns (state, period)."""
+                along="diagonal", shape=None):
+    """Fast wave of amplitude amp at time t (the exact linear solution).
+
+    along="diagonal": [0,1]^3, n^3 cells, k = 2 pi (1,1,1), period (1/sqrt 3)/c_f.
+    along="x": n x 1 x 1 cells, k = 2 pi x^.
+    along="box": shape = (nx, ny, nz) cells of equal spacing 1/nz, box
+    [0, nx/nz) x [0, ny/nz) x [0, 1), one wavelength across each side (the oblique
+    wave of a 512 x 512 x 256 benchmark box is shape=(512, 512, 256)).
+    Returns (state, period)."""
     if along == "diagonal":
         shape = (n, n, n)
         e1, e2, e3 = WAVE_FRAME
         kvec = 2.0 * math.pi * np.array([1.0, 1.0, 1.0])
-    else:
+        length = (1.0, 1.0, 1.0)
+    elif along == "x":
         shape = (n, 1, 1)
         e1, e2, e3 = np.eye(3)
         kvec = 2.0 * math.pi * np.array([1.0, 0.0, 0.0])
-    length = (1.0, shape[1] / n, shape[2] / n)
+        length = (1.0, 1.0 / n, 1.0 / n)
+    else:
+        shape = tuple(int(s) for s in shape)
+        n = shape[2]
+        length = (shape[0] / n, shape[1] / n, 1.0)
+        kvec, (e1, e2, e3) = box_wave_frame(length)
     rho0, p0 = 1.0, 1.0 / gamma
     cf, r = fast_eigenmode(rho0, p0, b0, gamma)
     kmag = float(np.linalg.norm(kvec))

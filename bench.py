@@ -77,20 +77,24 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, n_cells: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary of this
-    kernel class, if it was taken on the current kernel sources (else None)."""
+def measured_traffic(workload: str, kernel: str, n_cells: int):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3 counter summary
+    (calibrated FETCH_SIZE + WRITE_SIZE), if it was taken on the current kernel sources
+    and the same workload size (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         with open(path) as f:
             rec = json.load(f)
-        ent = rec.get("kernels", {}).get(kernel)
-        if not ent or rec.get("source_digest") != source_digest() or rec.get("n_cells") != n_cells:
+        if rec.get("source_digest") != source_digest():
+            return None
+        wl = rec.get("workloads", {}).get(workload, {})
+        ent = wl.get("kernels", {}).get(kernel)
+        if not ent or wl.get("n_cells") != n_cells:
             return None
         return float(ent["bytes_per_launch"])
-    except (OSError, ValueError, KeyError):
+    except (OSError, ValueError, KeyError, AttributeError):
         return None
 
 
@@ -124,7 +128,7 @@ def timed_run(sim, steps: int, warmup: int, dts_in=None):
     return el, times, warm, dts
 
 
-def kernel_roofline(times, table, ncell, alu_peak=None):
+def kernel_roofline(times, table, ncell, workload, alu_peak=None):
     """Roofline of the kernel class with the largest device time: achieved algorithmic
     bytes (and flops, where the table has them) per average launch duration."""
     dominant = max(times, key=lambda k: times[k][0])
@@ -142,7 +146,7 @@ def kernel_roofline(times, table, ncell, alu_peak=None):
         if f_alu > f_hbm:
             rf = {"bound": "alu", "achieved": round(tfl, 3), "peak": alu_peak, "unit": "TFLOP/s",
                   "frac": round(f_alu, 4)}
-    rf.update({"traffic": measured_traffic(dominant, ncell), "kernel": dominant,
+    rf.update({"traffic": measured_traffic(workload, dominant, ncell), "kernel": dominant,
                "avg_launch_ms": round(total_ms / launches, 4), "launches": launches,
                "hbm_frac": round(f_hbm, 4)})
     if f_alu is not None:
@@ -170,7 +174,7 @@ def dust_leg(n: int, steps: int, warmup: int, seed: int = 0):
                         f"g = 0.05, periodic {n}^3, IMEX2P+PLM+HLLE/Rusanov, CFL 0.3, seed {seed}",
             "value": round(value, 2), "unit": "Mzone-cycles/s", "dtype": "f64", "steps": steps,
             "ms_per_step": round(el * 1e3 / steps, 4),
-            "roofline": kernel_roofline(times, DUST_KERNEL_ALGO, ncell),
+            "roofline": kernel_roofline(times, DUST_KERNEL_ALGO, ncell, f"dust{n}_fp64"),
             "step_hbm_roofline": {"algo_bytes_per_zone_cycle": DUST_STEP_ALGO_BYTES,
                                   "frac": round(value * 1e6 * DUST_STEP_ALGO_BYTES
                                                 / (HBM_PEAK_GBS * 1e9), 4)},
@@ -289,13 +293,19 @@ def main():
     from paper_2608_14048_amd import Sim
     from paper_2608_14048_amd import inputs as I
 
+    copy_gbs = None
     if args.copy_probe:
-        # 2 GiB read + 2 GiB written per launch
+        # 2 GiB read + 2 GiB written per launch; the last two launches are timed
         src = torch.ones(1 << 28, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)
-        for _ in range(3):
+        dst.copy_(src)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(2):
             dst.copy_(src)
+        ev1.record()
         torch.cuda.synchronize()
+        copy_gbs = round(2 * 2 * src.numel() * 8 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9, 1)
         del src, dst
 
     n = args.n
@@ -311,7 +321,7 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     # roofline of the kernel class with the largest device time, against the resource
     # it is closer to saturating (HBM bytes or FP64 vector flops)
-    roofline = kernel_roofline(times, KERNEL_ALGO, ncell, FP64_VECTOR_PEAK_TFLOPS)
+    roofline = kernel_roofline(times, KERNEL_ALGO, ncell, f"turb{n}_fp64", FP64_VECTOR_PEAK_TFLOPS)
     kernel_ms = {k: round(v[0] / args.steps, 4) for k, v in sorted(times.items())}
 
     out = {
@@ -335,6 +345,8 @@ def main():
                               "frac": round(value * 1e6 * STEP_ALGO_BYTES / (HBM_PEAK_GBS * 1e9), 4)},
         "kernel_ms_per_step": kernel_ms,
     }
+    if copy_gbs is not None:
+        out["copy_probe_gbs"] = copy_gbs
     if not args.no_fp32:
         out["fp32_bulk"] = fp32_leg(n, state, warm_dts, dts, sim.state(device=True))
     sim.close()

@@ -14,10 +14,11 @@ region) and the CPU oracle timed on this host on a bounded sample of the same wo
 Side legs, each on its own workload and reported in its own object: the FP32-bulk form
 of the same run, the gas + 8 dust IMEX2P step at 192^3, and the RK2+PLM+HLLE oblique
 linear wave on a 512 x 512 x 256 box (the scheme and box of the paper's performance
-table).
+table), and 512 uneven meshblocks as one batch against the same blocks launched one by
+one.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--no-cpu-baseline]
-                       [--no-fp32] [--no-dust] [--no-paper-config]
+                       [--no-fp32] [--no-dust] [--no-paper-config] [--no-batch]
 """
 from __future__ import annotations
 
@@ -27,6 +28,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -211,6 +214,77 @@ def paper_config_leg(shape, steps: int, warmup: int, precisions=("fp64", "fp32_b
     return out
 
 
+def batch_leg(nblocks: int, steps: int, warmup: int, prec: str = "fp32_bulk", seed: int = 0):
+    """Batched uneven meshblocks: nblocks self-periodic blocks, each edge uniform in
+    {16, 24, 32, 48, 64} (seed), the turbulence recipe per block, VL2+PPM+HLLD+CT.
+    The batch (persistent launches, autotuned tile shapes) against the same blocks as
+    separate contexts (one launch sequence per block).  Both advance every block by its
+    own time step, fixed from the initial state, handed over from the host."""
+    import torch
+
+    from paper_2608_14048_amd import Batch, Sim
+    from paper_2608_14048_amd import inputs as I
+
+    print(f"[bench] batch leg: {nblocks} blocks ({prec})", file=sys.stderr, flush=True)
+    shapes = I.meshblock_shapes(nblocks, seed=seed)
+    states = [I.turbulence_block(sh, seed=1000 + b)[0] for b, sh in enumerate(shapes)]
+    ncell = int(sum(a * b * c for a, b, c in shapes))
+    scheme = dict(recon="ppm", riemann="hlld", integ="vl2", courant=0.3, prec=prec)
+    bt = Batch(shapes, scheme=scheme)
+    bt.set_state(states)
+    dts = bt.dt_cfl()
+    default_shapes = bt.tile_shapes()
+    tune_ms = bt.tune(reps=3)
+    chosen = bt.tile_shapes()
+
+    def run_batch():
+        for _ in range(warmup):
+            bt.step(dts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            bt.step(dts)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    bt.set_state(states)
+    el_tuned = run_batch()
+    bt.set_tile_shapes(default_shapes)
+    bt.set_state(states)
+    el_default = run_batch()
+    bt.close()
+    del bt
+    sims = []
+    for sh, st in zip(shapes, states):
+        sim = Sim(sh, tuple(v / max(sh) for v in sh), scheme=scheme)
+        sim.set_state(st)
+        sims.append(sim)
+    for _ in range(warmup):
+        for sim, dt in zip(sims, dts):
+            sim.step(dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for sim, dt in zip(sims, dts):
+            sim.step(dt)
+    torch.cuda.synchronize()
+    el_sep = time.perf_counter() - t0
+    for sim in sims:
+        sim.close()
+    mz = lambda el: round(ncell * steps / el / 1e6, 2)
+    classes = sorted(set(sh[0] for sh in shapes))
+    return {"workload": f"{nblocks} self-periodic blocks, edges uniform in {{16,24,32,48,64}} (seed {seed}), "
+                        f"{ncell / 1e6:.2f} M cells, turbulence per block, VL2+PPM+HLLD+CT, CFL 0.3",
+            "dtype": "f32 (E in f64)" if prec == "fp32_bulk" else "f64", "steps": steps,
+            "value": mz(el_tuned), "unit": "Mzone-cycles/s", "ms_per_step": round(el_tuned * 1e3 / steps, 4),
+            "default_shapes_value": mz(el_default),
+            "separate_launches_value": mz(el_sep),
+            "separate_launches_ms_per_step": round(el_sep * 1e3 / steps, 4),
+            "speedup_vs_separate": round(el_sep / el_tuned, 2),
+            "tuned_shape_per_x_extent": {str(x): int(np.argmin(tune_ms[q])) for q, x in enumerate(classes)},
+            "tune_ms_per_pass": {str(x): [round(float(v), 4) for v in tune_ms[q]] for q, x in enumerate(classes)}}
+
+
 def cpu_baseline(n: int, state, max_seconds: float = 30.0):
     """The oracle as it stands on a bounded sample: as many steps of the same workload
     as fit in about max_seconds (at least one)."""
@@ -272,6 +346,8 @@ def main():
     ap.add_argument("--no-dust", action="store_true", help="skip the gas + dust leg")
     ap.add_argument("--no-paper-config", action="store_true",
                     help="skip the RK2+PLM+HLLE linear-wave leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-meshblock leg")
+    ap.add_argument("--batch-blocks", type=int, default=512)
     ap.add_argument("--dust-n", type=int, default=192)
     ap.add_argument("--paper-shape", type=int, nargs=3, default=(512, 512, 256))
     ap.add_argument("--side-steps", type=int, default=50)
@@ -355,6 +431,8 @@ def main():
     if not args.no_paper_config:
         out["paper_config"] = paper_config_leg(tuple(args.paper_shape), args.side_steps,
                                                args.side_warmup)
+    if not args.no_batch:
+        out["batch"] = batch_leg(args.batch_blocks, max(args.side_steps // 5, 5), 2, "fp32_bulk", args.seed)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(n, state, args.cpu_seconds)

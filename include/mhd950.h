@@ -181,6 +181,65 @@ void mhd_destroy(mhd_ctx* ctx);
 /* Static description of a status code. */
 const char* mhd_strerror(mhd_status status);
 
+/* ---------------------------------------------------------------------------------
+ * Batched meshblocks.  The paper advances a list of meshblocks with the block index as
+ * one more launch dimension (Sec. "Mesh and Data Layout"; Table "MeshBlock").  A batch
+ * here is a set of nblocks INDEPENDENT self-periodic adiabatic-MHD boxes of any sizes
+ * sharing one physics and scheme; every stage kernel is one persistent launch that
+ * drains a device work queue of (block, tile, z chunk) items.  The stencil halo of
+ * each block (4 cells: PPM 3 + CT 1) is its own periodic wrap, so no ghost cells are
+ * stored.  Each block advances with its own time step.  A block advanced in a batch is
+ * bitwise identical to the same block advanced alone through mhd_step with the same dt.
+ *
+ * Ownership and errors as for a single context: the caller owns the workspace (256-byte
+ * aligned, mhd_batch_workspace_bytes) and the stream; the batch object is a small host
+ * object freed by mhd_batch_destroy.  After an MHD_E_DEVICE from a step the batch must
+ * be destroyed (its work counters may no longer match).  Dust (isothermal) batches are
+ * MHD_E_UNSUPPORTED; so are grids whose padded cell total reaches 2^29.
+ * --------------------------------------------------------------------------------- */
+typedef struct mhd_batch mhd_batch;
+
+/* Workspace bytes of a batch of nblocks grids (grids[b] is block b). */
+mhd_status mhd_batch_workspace_bytes(int nblocks, const mhd_grid* grids, const mhd_physics* phys,
+                                     const mhd_scheme* scheme, size_t* bytes);
+
+/* Carve a batch out of the caller's workspace; uploads the block table and the default
+ * work items (the widest tile that wastes no more lanes along x than the narrower). */
+mhd_status mhd_batch_create(int nblocks, const mhd_grid* grids, const mhd_physics* phys,
+                            const mhd_scheme* scheme, void* device_workspace, size_t bytes,
+                            void* hip_stream, mhd_batch** out);
+
+/* Doubles in the batch state: the sum over blocks of the single-context state length. */
+mhd_status mhd_batch_state_len(const mhd_batch* batch, size_t* n);
+
+/* The batch state is the blocks' canonical states concatenated in block order.  After
+ * set_state, each block's CFL step is on the device (see mhd_batch_step). */
+mhd_status mhd_batch_set_state(mhd_batch* batch, const double* src, int src_is_device);
+mhd_status mhd_batch_get_state(mhd_batch* batch, double* dst, int dst_is_device);
+
+/* Advance every block: block b by dt[b] (host array of nblocks positive finite values),
+ * or, with dt == NULL, by the CFL step of its current state that the device already
+ * holds (no host synchronisation).  Asynchronous on the stream. */
+mhd_status mhd_batch_step(mhd_batch* batch, const double* dt);
+
+/* The CFL step of every block's current state (nblocks doubles; synchronises);
+ * MHD_E_NONFINITE if any block holds NaN or Inf. */
+mhd_status mhd_batch_dt_cfl(mhd_batch* batch, double* dt);
+
+/* Tile shape per block: 0 = 64-wide tiles (64x4 flux, 64x8 update), 1 = 32-wide
+ * (32x8, 32x16), 2 = 16-wide (16x16, 16x32).  Results do not depend on the shapes. */
+mhd_status mhd_batch_set_shapes(mhd_batch* batch, const int* shapes, int nblocks);
+mhd_status mhd_batch_get_shapes(const mhd_batch* batch, int* shapes, int nblocks);
+
+/* Autotuner: for each class of blocks with one x extent (classes in increasing nx),
+ * time `reps` passes of the configured-reconstruction stage over that class alone with
+ * each tile shape, keep the fastest, and rebuild the work queue.  The current state is
+ * only read.  If ms_out is not NULL it receives the average ms per pass, class-major
+ * (nout >= classes * 3).  Synchronises the stream. */
+mhd_status mhd_batch_tune(mhd_batch* batch, int reps, float* ms_out, int nout);
+
+void mhd_batch_destroy(mhd_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -81,9 +81,27 @@ def load_library(path: str = LIB_PATH):
     L.mhd_timing_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int), ctypes.c_int]
     L.mhd_timing_name.argtypes = [ctypes.c_int]
     L.mhd_timing_name.restype = ctypes.c_char_p
+    ip = ctypes.POINTER(ctypes.c_int)
+    L.mhd_batch_workspace_bytes.argtypes = [ctypes.c_int, ctypes.POINTER(MhdGrid), ctypes.POINTER(MhdPhysics),
+                                            ctypes.POINTER(MhdScheme), ctypes.POINTER(sz)]
+    L.mhd_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(MhdGrid), ctypes.POINTER(MhdPhysics),
+                                   ctypes.POINTER(MhdScheme), vp, sz, vp, ctypes.POINTER(vp)]
+    L.mhd_batch_state_len.argtypes = [vp, ctypes.POINTER(sz)]
+    L.mhd_batch_set_state.argtypes = [vp, vp, ctypes.c_int]
+    L.mhd_batch_get_state.argtypes = [vp, vp, ctypes.c_int]
+    L.mhd_batch_step.argtypes = [vp, dp]
+    L.mhd_batch_dt_cfl.argtypes = [vp, dp]
+    L.mhd_batch_set_shapes.argtypes = [vp, ip, ctypes.c_int]
+    L.mhd_batch_get_shapes.argtypes = [vp, ip, ctypes.c_int]
+    L.mhd_batch_tune.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
+    L.mhd_batch_destroy.argtypes = [vp]
+    L.mhd_batch_destroy.restype = None
     for name in ("mhd_workspace_bytes", "mhd_create", "mhd_state_len", "mhd_set_state",
                  "mhd_get_state", "mhd_step", "mhd_dt_cfl", "mhd_diagnostics",
-                 "mhd_timing_enable", "mhd_timing_read"):
+                 "mhd_timing_enable", "mhd_timing_read", "mhd_batch_workspace_bytes",
+                 "mhd_batch_create", "mhd_batch_state_len", "mhd_batch_set_state",
+                 "mhd_batch_get_state", "mhd_batch_step", "mhd_batch_dt_cfl",
+                 "mhd_batch_set_shapes", "mhd_batch_get_shapes", "mhd_batch_tune"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -220,6 +238,86 @@ def mhd_timing_read(ctx: int) -> dict:
     return {names[q]: (float(ms[q]), int(cnt[q])) for q in range(len(names)) if cnt[q] > 0}
 
 
+def _grids(shapes, lengths):
+    arr = (MhdGrid * len(shapes))()
+    for b, sh in enumerate(shapes):
+        arr[b] = make_grid(sh, lengths[b])
+    return arr
+
+
+def mhd_batch_workspace_bytes(grids, phys: MhdPhysics, scheme: MhdScheme) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load_library().mhd_batch_workspace_bytes(len(grids), grids, ctypes.byref(phys),
+                                                    ctypes.byref(scheme), ctypes.byref(n)),
+           "mhd_batch_workspace_bytes")
+    return n.value
+
+
+def mhd_batch_create(grids, phys, scheme, workspace_ptr: int, nbytes: int, stream_ptr: int) -> int:
+    out = ctypes.c_void_p(0)
+    _check(load_library().mhd_batch_create(len(grids), grids, ctypes.byref(phys), ctypes.byref(scheme),
+                                           ctypes.c_void_p(workspace_ptr), ctypes.c_size_t(nbytes),
+                                           ctypes.c_void_p(stream_ptr), ctypes.byref(out)),
+           "mhd_batch_create")
+    return out.value
+
+
+def mhd_batch_state_len(b: int) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load_library().mhd_batch_state_len(ctypes.c_void_p(b), ctypes.byref(n)), "mhd_batch_state_len")
+    return n.value
+
+
+def mhd_batch_set_state(b: int, ptr: int, is_device: bool):
+    _check(load_library().mhd_batch_set_state(ctypes.c_void_p(b), ctypes.c_void_p(ptr), int(is_device)),
+           "mhd_batch_set_state")
+
+
+def mhd_batch_get_state(b: int, ptr: int, is_device: bool):
+    _check(load_library().mhd_batch_get_state(ctypes.c_void_p(b), ctypes.c_void_p(ptr), int(is_device)),
+           "mhd_batch_get_state")
+
+
+def mhd_batch_step(b: int, dts=None):
+    """dts: nblocks time steps, or None for each block's own CFL step (device-resident)."""
+    if dts is None:
+        _check(load_library().mhd_batch_step(ctypes.c_void_p(b), None), "mhd_batch_step")
+        return
+    a = np.ascontiguousarray(np.asarray(dts, dtype=np.float64))
+    _check(load_library().mhd_batch_step(ctypes.c_void_p(b), a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "mhd_batch_step")
+
+
+def mhd_batch_dt_cfl(b: int, nblocks: int) -> np.ndarray:
+    out = np.zeros(nblocks)
+    _check(load_library().mhd_batch_dt_cfl(ctypes.c_void_p(b), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "mhd_batch_dt_cfl")
+    return out
+
+
+def mhd_batch_set_shapes(b: int, shapes):
+    a = (ctypes.c_int * len(shapes))(*[int(v) for v in shapes])
+    _check(load_library().mhd_batch_set_shapes(ctypes.c_void_p(b), a, len(shapes)), "mhd_batch_set_shapes")
+
+
+def mhd_batch_get_shapes(b: int, nblocks: int):
+    a = (ctypes.c_int * nblocks)()
+    _check(load_library().mhd_batch_get_shapes(ctypes.c_void_p(b), a, nblocks), "mhd_batch_get_shapes")
+    return list(a)
+
+
+def mhd_batch_tune(b: int, reps: int, nclasses: int) -> np.ndarray:
+    """Autotune; returns the measured ms per pass, [class][shape]."""
+    out = (ctypes.c_float * (3 * nclasses))()
+    _check(load_library().mhd_batch_tune(ctypes.c_void_p(b), int(reps), out, 3 * nclasses), "mhd_batch_tune")
+    return np.array(list(out), dtype=np.float64).reshape(nclasses, 3)
+
+
+def mhd_batch_destroy(b: int):
+    if b:
+        load_library().mhd_batch_destroy(ctypes.c_void_p(b))
+
+
 # ---------------------------------------------------------------------------------
 # convenience object: Mesh + Simulation in one (cf. the paper's user interface)
 # ---------------------------------------------------------------------------------
@@ -303,6 +401,96 @@ class Sim:
     def close(self):
         if getattr(self, "ctx", 0):
             mhd_destroy(self.ctx)
+            self.ctx = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent self-periodic MHD blocks of uneven sizes advanced together (one
+    persistent launch per stage kernel and tile shape in use).
+
+    Batch(shapes, lengths, physics=dict(...), scheme=dict(...)); the state is the blocks'
+    canonical states concatenated in block order."""
+
+    def __init__(self, shapes, lengths=None, physics=None, scheme=None, device="cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the MI355X path has no CPU fallback")
+        load_library()
+        self.shapes = [tuple(int(v) for v in sh) for sh in shapes]
+        if lengths is None:
+            lengths = [tuple(v / max(sh) for v in sh) for sh in self.shapes]
+        self.lengths = [tuple(float(v) for v in L) for L in lengths]
+        self.nb = len(self.shapes)
+        self.device = torch.device(device)
+        self.grids = _grids(self.shapes, self.lengths)
+        self.phys = make_physics(**(physics or {}))
+        self.scheme = make_scheme(**(scheme or {}))
+        self.nbytes = mhd_batch_workspace_bytes(self.grids, self.phys, self.scheme)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = mhd_batch_create(self.grids, self.phys, self.scheme, self.workspace.data_ptr(),
+                                    self.nbytes, self.stream.cuda_stream)
+        self.n = mhd_batch_state_len(self.ctx)
+        self.classes = sorted(set(sh[0] for sh in self.shapes))
+
+    def block_slices(self):
+        """Slices of the concatenated state holding each block's canonical state."""
+        out, at = [], 0
+        for sh in self.shapes:
+            m = 8 * sh[0] * sh[1] * sh[2]
+            out.append(slice(at, at + m))
+            at += m
+        return out
+
+    def set_state(self, state):
+        import torch
+        if isinstance(state, (list, tuple)):
+            state = np.concatenate([np.asarray(s, dtype=np.float64).reshape(-1) for s in state])
+        if isinstance(state, torch.Tensor) and state.is_cuda:
+            t = state.detach().to(torch.float64).contiguous().reshape(-1)
+            assert t.numel() == self.n, (t.numel(), self.n)
+            mhd_batch_set_state(self.ctx, t.data_ptr(), True)
+            self._keep = t
+        else:
+            a = np.ascontiguousarray(np.asarray(state, dtype=np.float64).reshape(-1))
+            assert a.size == self.n, (a.size, self.n)
+            mhd_batch_set_state(self.ctx, a.ctypes.data, False)
+
+    def state(self, device: bool = False):
+        import torch
+        if device:
+            out = torch.empty(self.n, dtype=torch.float64, device=self.device)
+            mhd_batch_get_state(self.ctx, out.data_ptr(), True)
+            return out
+        a = np.empty(self.n, dtype=np.float64)
+        mhd_batch_get_state(self.ctx, a.ctypes.data, False)
+        return a
+
+    def step(self, dts=None):
+        mhd_batch_step(self.ctx, dts)
+
+    def dt_cfl(self) -> np.ndarray:
+        return mhd_batch_dt_cfl(self.ctx, self.nb)
+
+    def set_tile_shapes(self, shapes):
+        mhd_batch_set_shapes(self.ctx, shapes)
+
+    def tile_shapes(self):
+        return mhd_batch_get_shapes(self.ctx, self.nb)
+
+    def tune(self, reps: int = 3) -> np.ndarray:
+        return mhd_batch_tune(self.ctx, reps, len(self.classes))
+
+    def close(self):
+        if getattr(self, "ctx", 0):
+            mhd_batch_destroy(self.ctx)
             self.ctx = 0
 
     def __del__(self):

@@ -1,0 +1,737 @@
+// batch.hip -- many self-periodic meshblocks of uneven sizes advanced together.
+//
+// The paper runs a list of meshblocks with the block index as one more launch
+// dimension (Sec. "Mesh and Data Layout"); here the blocks are independent periodic
+// boxes of any sizes, and each stage kernel is one persistent launch per tile shape in
+// use (one launch for all blocks when they share a shape, three at most): a queue of
+// (block, tile, z chunk) work items, longest first, that the workgroups of the launch
+// drain through a device counter.  Tile shapes: 64x4 / 32x8 / 16x16 columns for the
+// flux kernel, 64x8 / 32x16 / 16x32 for the CT/update kernel; the shape of each
+// block-size class is picked by measurement (mhd_batch_tune).  A shape is a template
+// argument rather than a runtime switch because the three inlined tile bodies of one
+// kernel would not fit the register file together.  The tile bodies are the single-grid
+// ones (mhd_tiles.hpp), so a block advanced in a batch is bitwise identical to the same
+// block advanced alone.
+//
+// Work counter: a 64-bit device counter that only grows.  A launch over m items with g
+// workgroups takes exactly m + g values (every workgroup stops at its first fetch past
+// the end), so the host knows each launch's base without resetting anything.
+//
+// Each block advances by its own time step (the blocks are separate problems): the
+// step reads dt[b] from device memory, either written from the caller's host array or
+// left there by the CFL reduction of the previous step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "../../include/mhd950.h"
+#include "mhd_tiles.hpp"
+
+using namespace mhd;
+using namespace mhd::tiles;
+
+namespace {
+
+constexpr int kShapes = 3;
+constexpr int kFluxThreads = 256, kCtThreads = 512;
+constexpr int kFluxTX[kShapes] = {64, 32, 16};
+constexpr int kCtTX[kShapes] = {64, 32, 16};
+constexpr int kAlignCells = 64;  // block offsets in cells: keeps every field 256-B aligned
+
+struct BlockDesc {
+    Geo g;
+    unsigned long long off;  // first cell of the block in the batch
+};
+
+struct WorkItem {
+    int block, x0, y0, k0, k1, shape;
+};
+
+int flux_ty(int s) { return kFluxThreads / kFluxTX[s]; }
+int ct_ty(int s) { return kCtThreads / kCtTX[s]; }
+
+}  // namespace
+
+namespace mhd {
+
+// ----------------------------------------------------------------------------------
+// persistent stage kernels
+// ----------------------------------------------------------------------------------
+
+__device__ __forceinline__ int next_item(unsigned long long* ctr, unsigned long long base, int* slot)
+{
+    if (threadIdx.x == 0) *slot = (int)(long long)(atomicAdd(ctr, 1ULL) - base);
+    __syncthreads();
+    const int it = *slot;
+    __syncthreads();
+    return it;
+}
+
+template <int RECON, int RS, class R, int SHAPE>
+__global__ __launch_bounds__(kFluxThreads) void k_flux3_batch(const BlockDesc* __restrict__ blk,
+                                                             const WorkItem* __restrict__ items, int nitems,
+                                                             unsigned long long* ctr, unsigned long long base,
+                                                             MhdParams P, char* reg, int reg_bpc, R* F, R* Rc)
+{
+    constexpr int TX = SHAPE == 0 ? 64 : (SHAPE == 1 ? 32 : 16);
+    using Tile = FluxTile<RECON, RS, R, TX, kFluxThreads / TX>;
+    __shared__ typename Tile::Lds lds;
+    __shared__ int slot;
+    for (;;) {
+        const int it = next_item(ctr, base, &slot);
+        if (it < 0 || it >= nitems) break;
+        const WorkItem w = items[it];
+        const BlockDesc b = blk[w.block];
+        const RegView<R> U = reg_view<R>(reg + b.off * (unsigned long long)reg_bpc, b.g.n);
+        Tile::run(b.g, P, U, F + b.off * 21ULL, Rc + b.off * 3ULL, w.x0, w.y0, w.k0, w.k1, lds);
+        __syncthreads();  // the next item reuses the LDS
+    }
+}
+
+struct BatchCt {
+    char* in;
+    char* base;
+    char* out;
+    int reg_bpc;
+    double g0, g1, beta;  // out = g0 in + g1 base + beta dt[b] L
+    const double* dt;     // per block
+    double* partial;      // per item (CFL)
+};
+
+// items: this launch's items, which start at item id `first` of the whole list (the
+// CFL partial of item id q goes to partial[q]).
+template <bool CFL, bool IN, class R, int SHAPE>
+__global__ __launch_bounds__(kCtThreads) void k_ct_batch(const BlockDesc* __restrict__ blk,
+                                                        const WorkItem* __restrict__ items, int nitems, int first,
+                                                        unsigned long long* ctr, unsigned long long base,
+                                                        MhdParams P, BatchCt a, const R* F, const R* Rc)
+{
+    constexpr int TX = SHAPE == 0 ? 64 : (SHAPE == 1 ? 32 : 16);
+    using Tile = CtTile<CFL, IN, R, TX, kCtThreads / TX>;
+    __shared__ typename Tile::Lds lds;
+    __shared__ int slot;
+    __shared__ double sMin[kCtThreads / 64];
+    for (;;) {
+        const int it = next_item(ctr, base, &slot);
+        if (it < 0 || it >= nitems) break;
+        const WorkItem w = items[it];
+        const BlockDesc b = blk[w.block];
+        const unsigned long long ob = b.off * (unsigned long long)a.reg_bpc;
+        CtArgs<R> c{reg_view<R>(a.in + ob, b.g.n), reg_view<R>(a.base + ob, b.g.n), F + b.off * 21ULL,
+                    Rc + b.off * 3ULL, reg_view<R>(a.out + ob, b.g.n), nullptr,
+                    StageCoef{a.g0, a.g1, a.beta * a.dt[w.block]}};
+        double vmin = Tile::run(b.g, P, c, w.x0, w.y0, w.k0, w.k1, lds);
+        if (CFL) {
+            vmin = wave_min64(vmin);
+            if ((threadIdx.x & 63) == 0) sMin[threadIdx.x >> 6] = vmin;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double r = sMin[0];
+#pragma unroll
+                for (int q = 1; q < kCtThreads / 64; ++q) r = min_nan(r, sMin[q]);
+                a.partial[first + it] = r;
+            }
+        }
+        __syncthreads();  // the next item reuses the LDS
+    }
+}
+
+// dt[b] = scale * min of the CFL partials of block b's items (CSR lists).
+__global__ __launch_bounds__(256) void k_block_min(const double* __restrict__ partial,
+                                                   const int* __restrict__ start,
+                                                   const int* __restrict__ list, double scale,
+                                                   double* __restrict__ dt)
+{
+    __shared__ double sm[4];
+    const int b = blockIdx.x;
+    double r = INFINITY;
+    for (int q = start[b] + (int)threadIdx.x; q < start[b + 1]; q += 256) r = min_nan(r, partial[list[q]]);
+    r = wave_min64(r);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) dt[b] = scale * min_nan(min_nan(sm[0], sm[1]), min_nan(sm[2], sm[3]));
+}
+
+}  // namespace mhd
+
+// ----------------------------------------------------------------------------------
+// host runtime
+// ----------------------------------------------------------------------------------
+
+struct mhd_batch {
+    int nb;
+    std::vector<Geo> geo;
+    std::vector<unsigned long long> off;
+    unsigned long long ncell;  // padded total
+    mhd_physics phys;
+    mhd_scheme scheme;
+    MhdParams mp;
+    bool fp32;
+    int reg_bpc;  // register bytes per cell
+    hipStream_t stream;
+    int cus;
+    // workspace views
+    char* reg[3];
+    void* F;   // face fluxes; also the canonical FP64 staging area of the FP32-bulk form
+    void* Rc;
+    double* partial;
+    double* dt;            // per block
+    unsigned long long* ctr;  // [0] flux queue, [1] CT queue
+    BlockDesc* d_blk;
+    WorkItem* d_fitems;
+    WorkItem* d_citems;
+    int* d_cstart;
+    int* d_clist;
+    int cap_f, cap_c;      // item capacities
+    // host state
+    std::vector<int> shape;  // per block
+    int nf, nc;            // current item counts
+    int fbeg[kShapes + 1], cbeg[kShapes + 1];  // item ranges of each tile shape
+    unsigned long long base[2];
+    int cur;
+    double cfl_scale;
+};
+
+namespace {
+
+size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct BLayout {
+    size_t reg, F, Rc, partial, dt, ctr, blk, fitems, citems, cstart, clist, total;
+    unsigned long long ncell;
+    int cap_f, cap_c;
+    std::vector<unsigned long long> off;
+};
+
+int kz_of(int nz) { return nz < 64 ? nz : 64; }
+
+long long flux_items_of(const mhd_grid& g, int s)
+{
+    const int ty = flux_ty(s);
+    return (long long)((g.nx + kFluxTX[s] - 1) / kFluxTX[s]) * ((g.ny + ty - 1) / ty) *
+           ((g.nz + kz_of(g.nz) - 1) / kz_of(g.nz));
+}
+long long ct_items_of(const mhd_grid& g, int s)
+{
+    const int ty = ct_ty(s);
+    return (long long)((g.nx + kCtTX[s] - 1) / kCtTX[s]) * ((g.ny + ty - 1) / ty) *
+           ((g.nz + kz_of(g.nz) - 1) / kz_of(g.nz));
+}
+
+mhd_status bvalidate(int nb, const mhd_grid* grids, const mhd_physics* p, const mhd_scheme* s)
+{
+    if (nb < 1 || !grids || !p || !s) return MHD_E_INVAL;
+    if (p->eos != MHD_EOS_ADIABATIC_MHD || p->ndust != 0) return MHD_E_UNSUPPORTED;
+    if (s->integ != MHD_INT_VL2 && s->integ != MHD_INT_RK2 && s->integ != MHD_INT_EULER1)
+        return MHD_E_UNSUPPORTED;
+    if (s->prec != MHD_PREC_FP64 && s->prec != MHD_PREC_FP32_BULK) return MHD_E_UNSUPPORTED;
+    if (s->recon < MHD_RECON_DC || s->recon > MHD_RECON_PPM) return MHD_E_UNSUPPORTED;
+    if (s->riemann != MHD_RS_HLLE && s->riemann != MHD_RS_HLLD) return MHD_E_UNSUPPORTED;
+    if (!(s->courant > 0.0) || !std::isfinite(s->courant)) return MHD_E_INVAL;
+    if (!(p->gamma > 1.0)) return MHD_E_INVAL;
+    long long tot = 0;
+    for (int b = 0; b < nb; ++b) {
+        const mhd_grid& g = grids[b];
+        if (g.nx < 1 || g.ny < 1 || g.nz < 1) return MHD_E_INVAL;
+        for (int a = 0; a < 3; ++a)
+            if (!(g.length[a] > 0.0) || !std::isfinite(g.length[a])) return MHD_E_INVAL;
+        const long long n = (long long)g.nx * g.ny * g.nz;
+        tot += (n + kAlignCells - 1) / kAlignCells * kAlignCells;
+        // 32-bit offsets inside a block, and the whole batch below 2^29 cells
+        if (n >= (1LL << 29) || tot >= (1LL << 29)) return MHD_E_UNSUPPORTED;
+    }
+    return MHD_OK;
+}
+
+BLayout blayout(int nb, const mhd_grid* grids, const mhd_scheme* s)
+{
+    BLayout L;
+    const bool fp32 = s->prec == MHD_PREC_FP32_BULK;
+    const size_t rsz = fp32 ? sizeof(float) : sizeof(double);
+    unsigned long long o = 0;
+    long long cf = 0, cc = 0, maxblk = 1;
+    for (int b = 0; b < nb; ++b) {
+        const mhd_grid& g = grids[b];
+        const long long n = (long long)g.nx * g.ny * g.nz;
+        L.off.push_back(o);
+        o += (unsigned long long)((n + kAlignCells - 1) / kAlignCells * kAlignCells);
+        long long mf = 0, mc = 0;
+        for (int sh = 0; sh < kShapes; ++sh) {
+            mf = std::max(mf, flux_items_of(g, sh));
+            mc = std::max(mc, ct_items_of(g, sh));
+        }
+        cf += mf;
+        cc += mc;
+        maxblk = std::max(maxblk, (long long)blocks_for(n));
+    }
+    L.ncell = o;
+    L.cap_f = (int)cf;
+    L.cap_c = (int)cc;
+    L.reg = a256((size_t)o * register_bytes(1, fp32));
+    L.F = a256(std::max((size_t)o * 21 * rsz, (size_t)o * 8 * sizeof(double)));
+    L.Rc = a256((size_t)o * 3 * rsz);
+    L.partial = a256((size_t)std::max(cc, maxblk) * sizeof(double));
+    L.dt = a256((size_t)nb * sizeof(double));
+    L.ctr = a256(2 * sizeof(unsigned long long));
+    L.blk = a256((size_t)nb * sizeof(BlockDesc));
+    L.fitems = a256((size_t)cf * sizeof(WorkItem));
+    L.citems = a256((size_t)cc * sizeof(WorkItem));
+    L.cstart = a256((size_t)(nb + 1) * sizeof(int));
+    L.clist = a256((size_t)cc * sizeof(int));
+    L.total = 3 * L.reg + L.F + L.Rc + L.partial + L.dt + L.ctr + L.blk + L.fitems + L.citems + L.cstart +
+              L.clist;
+    return L;
+}
+
+mhd_status bdev(hipError_t e) { return e == hipSuccess ? MHD_OK : MHD_E_DEVICE; }
+
+// Default tile shape of a block: the widest tile that wastes no more lanes along x
+// than the narrower ones.
+int default_shape(int nx)
+{
+    int best = 0;
+    long long waste_best = -1;
+    for (int s = 0; s < kShapes; ++s) {
+        const long long waste = (long long)((nx + kFluxTX[s] - 1) / kFluxTX[s]) * kFluxTX[s] - nx;
+        if (waste_best < 0 || waste < waste_best) {
+            waste_best = waste;
+            best = s;
+        }
+    }
+    return best;
+}
+
+// Build both item lists (only blocks with include[b]), sorted by decreasing cost, and
+// the per-block CSR lists of CT items; upload them.
+mhd_status build_items(mhd_batch* c, const std::vector<char>& include)
+{
+    std::vector<WorkItem> fi, ci;
+    for (int b = 0; b < c->nb; ++b) {
+        if (!include[b]) continue;
+        const Geo& g = c->geo[b];
+        const int s = c->shape[b];
+        const int kz = kz_of(g.nz);
+        for (int k0 = 0; k0 < g.nz; k0 += kz)
+            for (int y0 = 0; y0 < g.ny; y0 += flux_ty(s))
+                for (int x0 = 0; x0 < g.nx; x0 += kFluxTX[s])
+                    fi.push_back(WorkItem{b, x0, y0, k0, std::min(k0 + kz, g.nz), s});
+        for (int k0 = 0; k0 < g.nz; k0 += kz)
+            for (int y0 = 0; y0 < g.ny; y0 += ct_ty(s))
+                for (int x0 = 0; x0 < g.nx; x0 += kCtTX[s])
+                    ci.push_back(WorkItem{b, x0, y0, k0, std::min(k0 + kz, g.nz), s});
+    }
+    // grouped by tile shape (one launch each), longest z chunks first within a shape
+    auto order = [](const WorkItem& a, const WorkItem& b) {
+        if (a.shape != b.shape) return a.shape < b.shape;
+        return a.k1 - a.k0 > b.k1 - b.k0;
+    };
+    std::stable_sort(fi.begin(), fi.end(), order);
+    std::stable_sort(ci.begin(), ci.end(), order);
+    for (int sh = 0; sh <= kShapes; ++sh) {
+        c->fbeg[sh] = (int)(std::lower_bound(fi.begin(), fi.end(), sh, [](const WorkItem& w, int v) { return w.shape < v; }) - fi.begin());
+        c->cbeg[sh] = (int)(std::lower_bound(ci.begin(), ci.end(), sh, [](const WorkItem& w, int v) { return w.shape < v; }) - ci.begin());
+    }
+    if ((int)fi.size() > c->cap_f || (int)ci.size() > c->cap_c) return MHD_E_NOMEM;
+    std::vector<int> start(c->nb + 1, 0), list(ci.size());
+    for (const WorkItem& w : ci) ++start[w.block + 1];
+    for (int b = 0; b < c->nb; ++b) start[b + 1] += start[b];
+    std::vector<int> fill(start.begin(), start.end() - 1);
+    for (int q = 0; q < (int)ci.size(); ++q) list[fill[ci[q].block]++] = q;
+    hipError_t e = hipSuccess;
+    if (!fi.empty()) e = hipMemcpyAsync(c->d_fitems, fi.data(), fi.size() * sizeof(WorkItem), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && !ci.empty())
+        e = hipMemcpyAsync(c->d_citems, ci.data(), ci.size() * sizeof(WorkItem), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->d_cstart, start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && !list.empty())
+        e = hipMemcpyAsync(c->d_clist, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // the host vectors go out of scope
+    c->nf = (int)fi.size();
+    c->nc = (int)ci.size();
+    return bdev(e);
+}
+
+mhd_status build_all(mhd_batch* c) { return build_items(c, std::vector<char>(c->nb, 1)); }
+
+int persistent_grid(const mhd_batch* c, int nitems) { return std::max(1, std::min(nitems, 4 * c->cus)); }
+
+template <int RECON, int RS, class R, int SH>
+void flux_launch(mhd_batch* c, char* in)
+{
+    const int m = c->fbeg[SH + 1] - c->fbeg[SH];
+    if (m == 0) return;
+    const int grid = persistent_grid(c, m);
+    hipLaunchKernelGGL((k_flux3_batch<RECON, RS, R, SH>), dim3(grid), dim3(kFluxThreads), 0, c->stream, c->d_blk,
+                       c->d_fitems + c->fbeg[SH], m, c->ctr, c->base[0], c->mp, in, c->reg_bpc, (R*)c->F, (R*)c->Rc);
+    c->base[0] += (unsigned long long)m + grid;
+}
+
+template <int RECON, int RS, class R>
+void flux_shapes(mhd_batch* c, char* in)
+{
+    flux_launch<RECON, RS, R, 0>(c, in);
+    flux_launch<RECON, RS, R, 1>(c, in);
+    flux_launch<RECON, RS, R, 2>(c, in);
+}
+
+template <class R>
+void flux_any(mhd_batch* c, int recon, char* in)
+{
+    if (c->scheme.riemann == MHD_RS_HLLD) {
+        if (recon == 0) flux_shapes<0, 1, R>(c, in);
+        else if (recon == 1) flux_shapes<1, 1, R>(c, in);
+        else flux_shapes<2, 1, R>(c, in);
+    } else {
+        if (recon == 0) flux_shapes<0, 0, R>(c, in);
+        else if (recon == 1) flux_shapes<1, 0, R>(c, in);
+        else flux_shapes<2, 0, R>(c, in);
+    }
+}
+
+template <bool CFL, bool IN, class R, int SH>
+void ct_launch(mhd_batch* c, const BatchCt& a)
+{
+    const int m = c->cbeg[SH + 1] - c->cbeg[SH];
+    if (m == 0) return;
+    const int grid = persistent_grid(c, m);
+    hipLaunchKernelGGL((k_ct_batch<CFL, IN, R, SH>), dim3(grid), dim3(kCtThreads), 0, c->stream, c->d_blk,
+                       c->d_citems + c->cbeg[SH], m, c->cbeg[SH], c->ctr + 1, c->base[1], c->mp, a,
+                       (const R*)c->F, (const R*)c->Rc);
+    c->base[1] += (unsigned long long)m + grid;
+}
+
+template <bool CFL, bool IN, class R>
+void ct_shapes(mhd_batch* c, const BatchCt& a)
+{
+    ct_launch<CFL, IN, R, 0>(c, a);
+    ct_launch<CFL, IN, R, 1>(c, a);
+    ct_launch<CFL, IN, R, 2>(c, a);
+}
+
+template <class R>
+void ct_any(mhd_batch* c, const BatchCt& a, bool cfl, bool use_in)
+{
+    if (cfl) {
+        if (use_in) ct_shapes<true, true, R>(c, a);
+        else ct_shapes<true, false, R>(c, a);
+    } else {
+        if (use_in) ct_shapes<false, true, R>(c, a);
+        else ct_shapes<false, false, R>(c, a);
+    }
+}
+
+// One stage over every block: fluxes of `in`, then out = g0 in + g1 base + beta dt L
+// (and, if last, the CFL step of out into dt[]).
+mhd_status bstage(mhd_batch* c, int recon, char* in, char* base, char* out, double g0, double g1,
+                  double beta, bool last)
+{
+    if (c->fp32) flux_any<float>(c, recon, in);
+    else flux_any<double>(c, recon, in);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return MHD_E_DEVICE;
+    BatchCt a{in, base, out, c->reg_bpc, g0, g1, beta, c->dt, c->partial};
+    const bool use_in = g0 != 0.0 || c->mp.gacc[0] != 0.0 || c->mp.gacc[1] != 0.0 || c->mp.gacc[2] != 0.0;
+    if (c->fp32) ct_any<float>(c, a, last, use_in);
+    else ct_any<double>(c, a, last, use_in);
+    e = hipGetLastError();
+    if (e != hipSuccess) return MHD_E_DEVICE;
+    if (last) {
+        hipLaunchKernelGGL(k_block_min, dim3(c->nb), dim3(256), 0, c->stream, c->partial, c->d_cstart, c->d_clist,
+                           c->cfl_scale, c->dt);
+        e = hipGetLastError();
+    }
+    return bdev(e);
+}
+
+mhd_status bstep(mhd_batch* c)
+{
+    const int s0 = c->cur, s1 = (c->cur + 1) % 3, s2 = (c->cur + 2) % 3;
+    char* S = c->reg[s0];
+    char* A = c->reg[s1];
+    char* B = c->reg[s2];
+    mhd_status st;
+    switch (c->scheme.integ) {
+    case MHD_INT_VL2:
+        st = bstage(c, MHD_RECON_DC, S, S, A, 0.0, 1.0, 0.5, false);
+        if (st != MHD_OK) return st;
+        st = bstage(c, c->scheme.recon, A, S, B, 0.0, 1.0, 1.0, true);
+        c->cur = s2;
+        return st;
+    case MHD_INT_RK2:
+        st = bstage(c, c->scheme.recon, S, S, A, 0.0, 1.0, 1.0, false);
+        if (st != MHD_OK) return st;
+        st = bstage(c, c->scheme.recon, A, S, B, 0.5, 0.5, 0.5, true);
+        c->cur = s2;
+        return st;
+    default:
+        st = bstage(c, c->scheme.recon, S, S, A, 0.0, 1.0, 1.0, true);
+        c->cur = s1;
+        return st;
+    }
+}
+
+// The canonical FP64 state of block b on the device (the register itself, or unpacked
+// into the staging area).
+const double* bcanon(mhd_batch* c, int b, hipError_t* e)
+{
+    *e = hipSuccess;
+    char* r = c->reg[c->cur] + c->off[b] * (unsigned long long)c->reg_bpc;
+    if (!c->fp32) return (const double*)r;
+    double* st = (double*)c->F + c->off[b] * 8ULL;
+    *e = launch_unpack_fp32(c->geo[b], r, st, c->stream);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+mhd_status mhd_batch_workspace_bytes(int nblocks, const mhd_grid* grids, const mhd_physics* phys,
+                                     const mhd_scheme* scheme, size_t* bytes)
+{
+    if (!bytes) return MHD_E_INVAL;
+    const mhd_status st = bvalidate(nblocks, grids, phys, scheme);
+    if (st != MHD_OK) return st;
+    *bytes = blayout(nblocks, grids, scheme).total;
+    return MHD_OK;
+}
+
+mhd_status mhd_batch_create(int nblocks, const mhd_grid* grids, const mhd_physics* phys,
+                            const mhd_scheme* scheme, void* workspace, size_t bytes, void* hip_stream,
+                            mhd_batch** out)
+{
+    if (!out) return MHD_E_INVAL;
+    *out = nullptr;
+    mhd_status st = bvalidate(nblocks, grids, phys, scheme);
+    if (st != MHD_OK) return st;
+    if (!workspace || ((uintptr_t)workspace & 255u)) return MHD_E_INVAL;
+    const BLayout L = blayout(nblocks, grids, scheme);
+    if (bytes < L.total) return MHD_E_NOMEM;
+    mhd_batch* c = new (std::nothrow) mhd_batch();
+    if (!c) return MHD_E_NOMEM;
+    c->nb = nblocks;
+    c->phys = *phys;
+    c->scheme = *scheme;
+    c->fp32 = scheme->prec == MHD_PREC_FP32_BULK;
+    c->reg_bpc = (int)register_bytes(1, c->fp32);
+    c->stream = (hipStream_t)hip_stream;
+    c->mp.gamma = phys->gamma;
+    c->mp.gm1inv = 1.0 / (phys->gamma - 1.0);
+    c->mp.rho_floor = phys->rho_floor;
+    c->mp.p_floor = phys->p_floor;
+    c->mp.hlld_eps = c->fp32 && scheme->hlld_eps < 1e-6 ? 1e-6 : scheme->hlld_eps;
+    for (int a = 0; a < 3; ++a) c->mp.gacc[a] = phys->gas_accel[a];
+    c->cfl_scale = scheme->courant;  // C_max = 1 for VL2, RK2 and EULER1
+    c->off = L.off;
+    c->ncell = L.ncell;
+    c->cap_f = L.cap_f;
+    c->cap_c = L.cap_c;
+    std::vector<BlockDesc> desc(nblocks);
+    for (int b = 0; b < nblocks; ++b) {
+        const mhd_grid& g = grids[b];
+        Geo q;
+        q.nx = g.nx; q.ny = g.ny; q.nz = g.nz;
+        q.n = (long long)g.nx * g.ny * g.nz;
+        const int ns[3] = {g.nx, g.ny, g.nz};
+        for (int a = 0; a < 3; ++a) {
+            q.dx[a] = g.length[a] / ns[a];
+            q.inv_dx[a] = 1.0 / q.dx[a];
+        }
+        c->geo.push_back(q);
+        desc[b] = BlockDesc{q, L.off[b]};
+        c->shape.push_back(default_shape(g.nx));
+    }
+    int dev = 0;
+    c->cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) c->cus = v;
+    }
+    char* p = (char*)workspace;
+    for (int r = 0; r < 3; ++r) {
+        c->reg[r] = p;
+        p += L.reg;
+    }
+    c->F = p; p += L.F;
+    c->Rc = p; p += L.Rc;
+    c->partial = (double*)p; p += L.partial;
+    c->dt = (double*)p; p += L.dt;
+    c->ctr = (unsigned long long*)p; p += L.ctr;
+    c->d_blk = (BlockDesc*)p; p += L.blk;
+    c->d_fitems = (WorkItem*)p; p += L.fitems;
+    c->d_citems = (WorkItem*)p; p += L.citems;
+    c->d_cstart = (int*)p; p += L.cstart;
+    c->d_clist = (int*)p;
+    c->base[0] = c->base[1] = 0;
+    c->cur = 0;
+    // counters start at zero; the block table and the default item lists go up once
+    const unsigned long long zero[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(c->ctr, zero, sizeof(zero), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->d_blk, desc.data(), desc.size() * sizeof(BlockDesc), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    st = e == hipSuccess ? build_all(c) : MHD_E_DEVICE;
+    if (st != MHD_OK) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    return MHD_OK;
+}
+
+mhd_status mhd_batch_state_len(const mhd_batch* c, size_t* n)
+{
+    if (!c || !n) return MHD_E_INVAL;
+    size_t t = 0;
+    for (const Geo& g : c->geo) t += (size_t)g.n * 8;
+    *n = t;
+    return MHD_OK;
+}
+
+mhd_status mhd_batch_set_state(mhd_batch* c, const double* src, int src_is_device)
+{
+    if (!c || !src) return MHD_E_INVAL;
+    hipError_t e = hipSuccess;
+    size_t at = 0;
+    for (int b = 0; b < c->nb && e == hipSuccess; ++b) {
+        const size_t nbytes = (size_t)c->geo[b].n * 8 * sizeof(double);
+        char* dst = c->fp32 ? (char*)c->F + c->off[b] * 64ULL : c->reg[c->cur] + c->off[b] * (unsigned long long)c->reg_bpc;
+        e = hipMemcpyAsync(dst, src + at, nbytes, src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                           c->stream);
+        at += (size_t)c->geo[b].n * 8;
+    }
+    if (e == hipSuccess && !src_is_device) e = hipStreamSynchronize(c->stream);
+    for (int b = 0; b < c->nb && e == hipSuccess; ++b) {
+        const double* canon = c->fp32 ? (const double*)((char*)c->F + c->off[b] * 64ULL)
+                                      : (const double*)(c->reg[c->cur] + c->off[b] * (unsigned long long)c->reg_bpc);
+        e = launch_cfl_mhd(c->geo[b], c->mp, canon, c->partial, c->dt + b, c->cfl_scale, c->stream);
+        if (e == hipSuccess && c->fp32)
+            e = launch_pack_fp32(c->geo[b], canon, c->reg[c->cur] + c->off[b] * (unsigned long long)c->reg_bpc, c->stream);
+    }
+    return bdev(e);
+}
+
+mhd_status mhd_batch_get_state(mhd_batch* c, double* dst, int dst_is_device)
+{
+    if (!c || !dst) return MHD_E_INVAL;
+    hipError_t e = hipSuccess;
+    size_t at = 0;
+    for (int b = 0; b < c->nb && e == hipSuccess; ++b) {
+        const double* canon = bcanon(c, b, &e);
+        if (e != hipSuccess) break;
+        const size_t nbytes = (size_t)c->geo[b].n * 8 * sizeof(double);
+        e = hipMemcpyAsync(dst + at, canon, nbytes, dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           c->stream);
+        at += (size_t)c->geo[b].n * 8;
+    }
+    if (e == hipSuccess && !dst_is_device) e = hipStreamSynchronize(c->stream);
+    return bdev(e);
+}
+
+mhd_status mhd_batch_step(mhd_batch* c, const double* dt)
+{
+    if (!c) return MHD_E_INVAL;
+    if (dt) {
+        for (int b = 0; b < c->nb; ++b)
+            if (!(dt[b] > 0.0) || !std::isfinite(dt[b])) return MHD_E_INVAL;
+        hipError_t e = hipMemcpyAsync(c->dt, dt, (size_t)c->nb * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) return MHD_E_DEVICE;
+    }
+    return bstep(c);
+}
+
+mhd_status mhd_batch_dt_cfl(mhd_batch* c, double* dt)
+{
+    if (!c || !dt) return MHD_E_INVAL;
+    hipError_t e = hipMemcpyAsync(dt, c->dt, (size_t)c->nb * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return MHD_E_DEVICE;
+    for (int b = 0; b < c->nb; ++b)
+        if (!std::isfinite(dt[b]) || !(dt[b] > 0.0)) return MHD_E_NONFINITE;
+    return MHD_OK;
+}
+
+mhd_status mhd_batch_set_shapes(mhd_batch* c, const int* shapes, int n)
+{
+    if (!c || !shapes || n != c->nb) return MHD_E_INVAL;
+    for (int b = 0; b < n; ++b)
+        if (shapes[b] < 0 || shapes[b] >= kShapes) return MHD_E_INVAL;
+    for (int b = 0; b < n; ++b) c->shape[b] = shapes[b];
+    return build_all(c);
+}
+
+mhd_status mhd_batch_get_shapes(const mhd_batch* c, int* shapes, int n)
+{
+    if (!c || !shapes || n != c->nb) return MHD_E_INVAL;
+    for (int b = 0; b < n; ++b) shapes[b] = c->shape[b];
+    return MHD_OK;
+}
+
+mhd_status mhd_batch_tune(mhd_batch* c, int reps, float* ms_out, int nout)
+{
+    if (!c || reps < 1) return MHD_E_INVAL;
+    // classes: blocks of one x extent share a tile shape
+    std::vector<int> xs;
+    for (const Geo& g : c->geo) xs.push_back(g.nx);
+    std::sort(xs.begin(), xs.end());
+    xs.erase(std::unique(xs.begin(), xs.end()), xs.end());
+    if (ms_out && nout < (int)xs.size() * kShapes) return MHD_E_INVAL;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return MHD_E_DEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return MHD_E_DEVICE;
+    }
+    const std::vector<int> saved = c->shape;
+    std::vector<int> best(xs.size(), 0);
+    mhd_status st = MHD_OK;
+    const int s0 = c->cur, s1 = (c->cur + 1) % 3;
+    for (size_t q = 0; q < xs.size() && st == MHD_OK; ++q) {
+        std::vector<char> inc(c->nb);
+        for (int b = 0; b < c->nb; ++b) inc[b] = c->geo[b].nx == xs[q];
+        float tbest = 0.0f;
+        for (int s = 0; s < kShapes && st == MHD_OK; ++s) {
+            for (int b = 0; b < c->nb; ++b)
+                if (inc[b]) c->shape[b] = s;
+            st = build_items(c, inc);
+            if (st != MHD_OK) break;
+            // the configured-reconstruction stage into the scratch register (the state
+            // itself is only read); one untimed pass, then reps timed
+            float ms = 0.0f;
+            for (int r = 0; r <= reps && st == MHD_OK; ++r) {
+                if (r == 1 && hipEventRecord(e0, c->stream) != hipSuccess) st = MHD_E_DEVICE;
+                if (st == MHD_OK)
+                    st = bstage(c, c->scheme.recon, c->reg[s0], c->reg[s0], c->reg[s1], 0.0, 1.0, 1.0, false);
+            }
+            if (st == MHD_OK && hipEventRecord(e1, c->stream) != hipSuccess) st = MHD_E_DEVICE;
+            if (st == MHD_OK && hipEventSynchronize(e1) != hipSuccess) st = MHD_E_DEVICE;
+            if (st == MHD_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = MHD_E_DEVICE;
+            if (st != MHD_OK) break;
+            if (ms_out) ms_out[q * kShapes + s] = ms / reps;
+            if (s == 0 || ms < tbest) {
+                tbest = ms;
+                best[q] = s;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != MHD_OK) {
+        c->shape = saved;
+        (void)build_all(c);
+        return st;
+    }
+    for (int b = 0; b < c->nb; ++b)
+        c->shape[b] = best[std::lower_bound(xs.begin(), xs.end(), c->geo[b].nx) - xs.begin()];
+    return build_all(c);
+}
+
+void mhd_batch_destroy(mhd_batch* c) { delete c; }
+
+}  // extern "C"

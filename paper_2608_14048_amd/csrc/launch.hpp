@@ -39,7 +39,7 @@ struct RegView {
     double* E;
 };
 template <class R>
-inline RegView<R> reg_view(void* base, long long n)
+__host__ __device__ inline RegView<R> reg_view(void* base, long long n)
 {
     RegView<R> v;
     if constexpr (sizeof(R) == sizeof(double)) {

@@ -44,6 +44,10 @@ __device__ __forceinline__ double min_r(double a, double b) { return fmin(a, b);
 __device__ __forceinline__ float min_r(float a, float b) { return fminf(a, b); }
 __device__ __forceinline__ double max_r(double a, double b) { return fmax(a, b); }
 __device__ __forceinline__ float max_r(float a, float b) { return fmaxf(a, b); }
+// a * b + c with one rounding (written out where a formula wants it, so that the
+// rounding of a helper does not depend on where the compiler inlines it)
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 // a / b: IEEE division in FP64, a times the hardware reciprocal in FP32
 __device__ __forceinline__ double div_r(double a, double b) { return a / b; }
 __device__ __forceinline__ float div_r(float a, float b) { return a * rcp(b); }
@@ -52,10 +56,16 @@ __device__ __forceinline__ float div_r(float a, float b) { return a * rcp(b); }
 // reconstruction of one scalar on the face between cells s[2] and s[3]
 // ----------------------------------------------------------------------------------
 
+// The reconstruction helpers keep every rounding explicit (no contraction left to the
+// compiler): a z pipeline primed at the start of a chunk then reproduces bit for bit
+// the values it would carry from the plane before, so results do not depend on how the
+// z planes are split among workgroups.
+
 // van Leer's monotonized harmonic mean of the one-sided differences.
 template <class R>
 __device__ __forceinline__ R slope_vl(R am, R a0, R ap)
 {
+#pragma clang fp contract(off)
     const R dm = a0 - am, dp = ap - a0;
     const R pr = dm * dp;
     return pr > R(0) ? div_r(R(2) * pr, dm + dp) : R(0);
@@ -65,6 +75,7 @@ __device__ __forceinline__ R slope_vl(R am, R a0, R ap)
 template <class R>
 __device__ __forceinline__ R cw_slope(R am, R a0, R ap)
 {
+#pragma clang fp contract(off)
     const R dm = a0 - am, dp = ap - a0;
     if (!(dm * dp > R(0))) return R(0);
     const R c = R(0.5) * (ap - am);
@@ -73,29 +84,34 @@ __device__ __forceinline__ R cw_slope(R am, R a0, R ap)
 }
 
 // Colella-Woodward interface value between cells a0 and a1 from their limited slopes
-// (the fourth-order average, monotonised through the slopes).
+// (the fourth-order average, monotonised through the slopes):
+// a0 + (a1 - a0)/2 - (m1 - m0)/6.
 template <class R>
 __device__ __forceinline__ R cw_interface(R a0, R a1, R m0, R m1)
 {
-    return a0 + R(0.5) * (a1 - a0) - (m1 - m0) * R(1.0 / 6.0);
+#pragma clang fp contract(off)
+    const R t = fma_r(R(0.5), a1 - a0, a0);
+    return fma_r(m0 - m1, R(1.0 / 6.0), t);
 }
 
 // Colella-Woodward monotonisation of a parabola (centre a, edges lo, hi).
 template <class R>
 __device__ __forceinline__ void cw_limit(R a, R& lo, R& hi)
 {
+#pragma clang fp contract(off)
     if ((hi - a) * (a - lo) <= R(0)) {
         lo = a;
         hi = a;
         return;
     }
     const R da = hi - lo;
-    const R a6 = R(6) * (a - R(0.5) * (lo + hi));
+    const R a6 = R(6) * fma_r(R(-0.5), lo + hi, a);
     const R da2 = da * da;
-    if (da * a6 > da2)
-        lo = R(3) * a - R(2) * hi;
-    else if (-da2 > da * a6)
-        hi = R(3) * a - R(2) * lo;
+    const R p = da * a6;
+    if (p > da2)
+        lo = fma_r(R(-2), hi, R(3) * a);
+    else if (-da2 > p)
+        hi = fma_r(R(-2), lo, R(3) * a);
 }
 
 template <int RECON, class R>
@@ -114,8 +130,8 @@ template <class R>
 struct FaceStates<1, R> {
     __device__ static void get(const R* s, R& aL, R& aR)
     {
-        aL = s[2] + R(0.5) * slope_vl(s[1], s[2], s[3]);
-        aR = s[3] - R(0.5) * slope_vl(s[2], s[3], s[4]);
+        aL = fma_r(R(0.5), slope_vl(s[1], s[2], s[3]), s[2]);
+        aR = fma_r(R(-0.5), slope_vl(s[2], s[3], s[4]), s[3]);
     }
 };
 

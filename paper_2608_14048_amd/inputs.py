@@ -241,6 +241,63 @@ def turbulence(n=256, seed=0, gamma=5.0 / 3.0, sigma_lnrho=0.1, mach=1.0, beta=1
     return state
 
 
+def _random_field_box(rng, shape, length, kmin, kmax, slope_amp, shift):
+    """Real Gaussian random field on an nx x ny x nz periodic box of side lengths
+    `length`, sampled at offset `shift` (fractions of a cell per axis x,y,z): Fourier
+    amplitudes ~ |k|^slope_amp for kmin <= |k| <= kmax, |k| in units of 2 pi."""
+    nx, ny, nz = shape
+    fx = np.fft.rfftfreq(nx, d=1.0 / nx)
+    fy = np.fft.fftfreq(ny, d=1.0 / ny)
+    fz = np.fft.fftfreq(nz, d=1.0 / nz)
+    MZ, MY, MX = np.meshgrid(fz, fy, fx, indexing="ij")  # integer mode numbers
+    kk = np.sqrt((MX / length[0]) ** 2 + (MY / length[1]) ** 2 + (MZ / length[2]) ** 2)
+    band = (kk >= kmin) & (kk <= kmax)
+    amp = np.zeros_like(kk)
+    amp[band] = kk[band] ** slope_amp
+    spec = (rng.standard_normal(kk.shape) + 1j * rng.standard_normal(kk.shape)) * amp
+    phase = np.exp(2j * math.pi * (MX * shift[0] / nx + MY * shift[1] / ny + MZ * shift[2] / nz))
+    return np.fft.irfftn(spec * phase, s=(nz, ny, nx), axes=(0, 1, 2))
+
+
+def turbulence_block(shape, seed=0, gamma=5.0 / 3.0, sigma_lnrho=0.1, mach=1.0, beta=1.0,
+                     kmin=2.0, kmax=8.0):
+    """The turbulence recipe on one self-periodic block of nx x ny x nz cells with equal
+    spacing, box lengths n_a / max(n) (the longest side is 1).  Returns (state, length)."""
+    nx, ny, nz = (int(v) for v in shape)
+    nmax = max(nx, ny, nz)
+    length = (nx / nmax, ny / nmax, nz / nmax)
+    rng = np.random.default_rng(seed)
+    full = (nz, ny, nx)
+    p0 = 1.0 / gamma
+    rho = np.exp(sigma_lnrho * rng.standard_normal(full))
+    vel = [_random_field_box(rng, (nx, ny, nz), length, kmin, kmax, -2.0, (0.0, 0.0, 0.0))
+           for _ in range(3)]
+    vel = [v - v.mean() for v in vel]
+    vrms = math.sqrt(float(np.mean(vel[0] ** 2 + vel[1] ** 2 + vel[2] ** 2)))
+    vel = [v * (mach / vrms) for v in vel]
+    shifts = [(0.0, -0.5, -0.5), (-0.5, 0.0, -0.5), (-0.5, -0.5, 0.0)]
+    pots = [_random_field_box(rng, (nx, ny, nz), length, kmin, kmax, -3.0, shifts[a])
+            for a in range(3)]
+    h = 1.0 / nmax
+    b1, b2, b3 = faces_from_potential(*pots, h, h, h)
+    bx, by, bz = cell_centred_field(b1, b2, b3)
+    b2mean = float(np.mean(bx * bx + by * by + bz * bz))
+    scale = math.sqrt(2.0 * p0 / beta / b2mean)
+    b1, b2, b3 = b1 * scale, b2 * scale, b3 * scale
+    eint = np.full(full, p0 / (gamma - 1.0))
+    return mhd_state(rho, vel[0], vel[1], vel[2], eint, b1, b2, b3), length
+
+
+BLOCK_EDGES = (16, 24, 32, 48, 64)
+
+
+def meshblock_shapes(nblocks=512, seed=0, edges=BLOCK_EDGES):
+    """Block shapes of the batched workload: each edge drawn independently and
+    uniformly from `edges` (numpy PCG64 `seed`)."""
+    rng = np.random.default_rng(seed)
+    return [tuple(int(e) for e in rng.choice(edges, size=3)) for _ in range(nblocks)]
+
+
 # ---------------------------------------------------------------------------------
 # gas + dust under a gas-only acceleration (terminal drift + noise)
 # ---------------------------------------------------------------------------------

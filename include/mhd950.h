@@ -240,6 +240,67 @@ mhd_status mhd_batch_tune(mhd_batch* batch, int reps, float* ms_out, int nout);
 
 void mhd_batch_destroy(mhd_batch* batch);
 
+/* ---------------------------------------------------------------------------------
+ * Learned subgrid flux-correction closure of the coarse step.  The paper lists learned
+ * closures as future work (Sec. "Conclusions"); the network here sees the 8 primitive
+ * channels (rho, v, p, B_cc) of the coarse state at the start of a step, normalised as
+ * (w - mu) / sd, and returns 18 channels per cell: face-flux corrections of rho, M_x,
+ * M_y, M_z, E through the low x, y, z faces (channel 3 f + d, scaled by sF[f]) and
+ * edge-EMF corrections E_x, E_y, E_z on the cell's low edges (channels 15..17, scaled
+ * by sE).  They enter the plain step in flux form (eq. (fv_update)) and in
+ * constrained-transport form (eq. (ct)): U_f -= dt sum_d (dF[c+e_d] - dF[c]) / dx_d,
+ * b -= dt curl(dE); mass, momentum and energy stay conservative and div B unchanged.
+ * Network: 4 periodic 3x3x3 convolutions 8 -> 32 -> 32 -> 32 -> 18, ReLU after the
+ * first three; BF16 operands on the matrix cores, FP32 accumulation; FP32 master
+ * weights and Adam.  Parameters, in order, per layer: W [27][cin][cout] with tap
+ * t = (dz+1)*9 + (dy+1)*3 + (dx+1) (y[v][co] = b[co] + sum W[t][ci][co] x[v+off(t)][ci]),
+ * then b [cout].  Grids: adiabatic MHD, nx a multiple of 16, fewer than 2^26 cells
+ * (else MHD_E_UNSUPPORTED).  Device pointers are canonical FP64 states (8 fields).
+ * Ownership as for a context: caller's workspace and stream; calls on one network are
+ * not thread safe.
+ * --------------------------------------------------------------------------------- */
+typedef struct mhd_cnn mhd_cnn;
+
+mhd_status mhd_cnn_param_count(size_t* n);
+mhd_status mhd_cnn_workspace_bytes(const mhd_grid* grid, const mhd_physics* phys, size_t* bytes);
+/* Parameters and Adam moments start at zero (the closure is then exactly zero). */
+mhd_status mhd_cnn_create(const mhd_grid* grid, const mhd_physics* phys, void* device_workspace,
+                          size_t bytes, void* hip_stream, mhd_cnn** out);
+/* Host FP32 arrays of mhd_cnn_param_count values (synchronising). */
+mhd_status mhd_cnn_set_params(mhd_cnn* cnn, const float* params);
+mhd_status mhd_cnn_get_params(mhd_cnn* cnn, float* params);
+mhd_status mhd_cnn_get_grads(mhd_cnn* cnn, float* grads);
+/* Input normalisation mu[8], sd[8] (> 0); output scales sF[5], sE; loss weights wU[5]
+ * for rho, M_x, M_y, M_z, E and wB for each face field. */
+mhd_status mhd_cnn_set_scales(mhd_cnn* cnn, const float* mu, const float* sd, const float* sF, float sE,
+                              const float* wU, float wB);
+/* Network output of a state into the network's output buffer; mhd_cnn_output copies it
+ * out as FP32 [18][nz][ny][nx]. */
+mhd_status mhd_cnn_forward(mhd_cnn* cnn, const double* state);
+mhd_status mhd_cnn_output(mhd_cnn* cnn, float* dst, int dst_is_device);
+/* Add the corrections of the last forward pass to a state, in place. */
+mhd_status mhd_closure_apply(mhd_cnn* cnn, double dt, double* state);
+/* One training sample: forward from state_t, closure applied to coarse_next (the plain
+ * coarse step of state_t by dt), loss sum_f w_f (pred - target)^2 / cells against the
+ * filtered fine state, gradients ADDED to the network's gradient buffer; *loss (if not
+ * NULL) receives the loss (synchronising). */
+mhd_status mhd_cnn_zero_grad(mhd_cnn* cnn);
+mhd_status mhd_cnn_accumulate(mhd_cnn* cnn, const double* state_t, const double* coarse_next,
+                              const double* target, double dt, double* loss);
+/* Adam step `step` (>= 1) on grad_scale * gradients. */
+mhd_status mhd_cnn_adam(mhd_cnn* cnn, float lr, float beta1, float beta2, float eps, int step,
+                        float grad_scale);
+/* One closure step of a context: corrections from its current state, the plain step by
+ * dt, the corrections added (the context's CFL step is refreshed).  The context's grid
+ * must be the network's. */
+mhd_status mhd_step_closure(mhd_ctx* ctx, mhd_cnn* cnn, double dt);
+/* Box filter of a fine canonical state (device) onto the grid r times coarser: cell
+ * fields averaged over r^3 cells, face fields over the r^2 fine faces of each coarse
+ * face (so the coarse div B is the mean of the fine one).  Asynchronous. */
+mhd_status mhd_box_filter(const mhd_grid* fine, int r, const double* fine_state, double* coarse_state,
+                          void* hip_stream);
+void mhd_cnn_destroy(mhd_cnn* cnn);
+
 #ifdef __cplusplus
 }
 #endif

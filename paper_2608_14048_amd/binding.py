@@ -96,12 +96,35 @@ def load_library(path: str = LIB_PATH):
     L.mhd_batch_tune.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
     L.mhd_batch_destroy.argtypes = [vp]
     L.mhd_batch_destroy.restype = None
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.mhd_cnn_param_count.argtypes = [ctypes.POINTER(sz)]
+    L.mhd_cnn_workspace_bytes.argtypes = [ctypes.POINTER(MhdGrid), ctypes.POINTER(MhdPhysics), ctypes.POINTER(sz)]
+    L.mhd_cnn_create.argtypes = [ctypes.POINTER(MhdGrid), ctypes.POINTER(MhdPhysics), vp, sz, vp, ctypes.POINTER(vp)]
+    L.mhd_cnn_set_params.argtypes = [vp, fp]
+    L.mhd_cnn_get_params.argtypes = [vp, fp]
+    L.mhd_cnn_get_grads.argtypes = [vp, fp]
+    L.mhd_cnn_set_scales.argtypes = [vp, fp, fp, fp, ctypes.c_float, fp, ctypes.c_float]
+    L.mhd_cnn_forward.argtypes = [vp, vp]
+    L.mhd_cnn_output.argtypes = [vp, vp, ctypes.c_int]
+    L.mhd_closure_apply.argtypes = [vp, ctypes.c_double, vp]
+    L.mhd_cnn_zero_grad.argtypes = [vp]
+    L.mhd_cnn_accumulate.argtypes = [vp, vp, vp, vp, ctypes.c_double, dp]
+    L.mhd_cnn_adam.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int,
+                               ctypes.c_float]
+    L.mhd_step_closure.argtypes = [vp, vp, ctypes.c_double]
+    L.mhd_box_filter.argtypes = [ctypes.POINTER(MhdGrid), ctypes.c_int, vp, vp, vp]
+    L.mhd_cnn_destroy.argtypes = [vp]
+    L.mhd_cnn_destroy.restype = None
     for name in ("mhd_workspace_bytes", "mhd_create", "mhd_state_len", "mhd_set_state",
                  "mhd_get_state", "mhd_step", "mhd_dt_cfl", "mhd_diagnostics",
                  "mhd_timing_enable", "mhd_timing_read", "mhd_batch_workspace_bytes",
                  "mhd_batch_create", "mhd_batch_state_len", "mhd_batch_set_state",
                  "mhd_batch_get_state", "mhd_batch_step", "mhd_batch_dt_cfl",
-                 "mhd_batch_set_shapes", "mhd_batch_get_shapes", "mhd_batch_tune"):
+                 "mhd_batch_set_shapes", "mhd_batch_get_shapes", "mhd_batch_tune",
+                 "mhd_cnn_param_count", "mhd_cnn_workspace_bytes", "mhd_cnn_create", "mhd_cnn_set_params",
+                 "mhd_cnn_get_params", "mhd_cnn_get_grads", "mhd_cnn_set_scales", "mhd_cnn_forward",
+                 "mhd_cnn_output", "mhd_closure_apply", "mhd_cnn_zero_grad", "mhd_cnn_accumulate",
+                 "mhd_cnn_adam", "mhd_step_closure", "mhd_box_filter"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -318,6 +341,102 @@ def mhd_batch_destroy(b: int):
         load_library().mhd_batch_destroy(ctypes.c_void_p(b))
 
 
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def mhd_cnn_param_count() -> int:
+    n = ctypes.c_size_t(0)
+    _check(load_library().mhd_cnn_param_count(ctypes.byref(n)), "mhd_cnn_param_count")
+    return n.value
+
+
+def mhd_cnn_workspace_bytes(grid: MhdGrid, phys: MhdPhysics) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load_library().mhd_cnn_workspace_bytes(ctypes.byref(grid), ctypes.byref(phys), ctypes.byref(n)),
+           "mhd_cnn_workspace_bytes")
+    return n.value
+
+
+def mhd_cnn_create(grid, phys, workspace_ptr: int, nbytes: int, stream_ptr: int) -> int:
+    out = ctypes.c_void_p(0)
+    _check(load_library().mhd_cnn_create(ctypes.byref(grid), ctypes.byref(phys), ctypes.c_void_p(workspace_ptr),
+                                         ctypes.c_size_t(nbytes), ctypes.c_void_p(stream_ptr), ctypes.byref(out)),
+           "mhd_cnn_create")
+    return out.value
+
+
+def mhd_cnn_set_params(cnn: int, params):
+    a = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+    _check(load_library().mhd_cnn_set_params(ctypes.c_void_p(cnn), _fptr(a)), "mhd_cnn_set_params")
+
+
+def mhd_cnn_get_params(cnn: int) -> np.ndarray:
+    a = np.zeros(mhd_cnn_param_count(), dtype=np.float32)
+    _check(load_library().mhd_cnn_get_params(ctypes.c_void_p(cnn), _fptr(a)), "mhd_cnn_get_params")
+    return a
+
+
+def mhd_cnn_get_grads(cnn: int) -> np.ndarray:
+    a = np.zeros(mhd_cnn_param_count(), dtype=np.float32)
+    _check(load_library().mhd_cnn_get_grads(ctypes.c_void_p(cnn), _fptr(a)), "mhd_cnn_get_grads")
+    return a
+
+
+def mhd_cnn_set_scales(cnn: int, mu, sd, sF, sE: float, wU, wB: float):
+    f = lambda v: np.ascontiguousarray(np.asarray(v, dtype=np.float32))
+    mu, sd, sF, wU = f(mu), f(sd), f(sF), f(wU)
+    _check(load_library().mhd_cnn_set_scales(ctypes.c_void_p(cnn), _fptr(mu), _fptr(sd), _fptr(sF), float(sE),
+                                             _fptr(wU), float(wB)), "mhd_cnn_set_scales")
+
+
+def mhd_cnn_forward(cnn: int, state_ptr: int):
+    _check(load_library().mhd_cnn_forward(ctypes.c_void_p(cnn), ctypes.c_void_p(state_ptr)), "mhd_cnn_forward")
+
+
+def mhd_cnn_output(cnn: int, ptr: int, is_device: bool):
+    _check(load_library().mhd_cnn_output(ctypes.c_void_p(cnn), ctypes.c_void_p(ptr), int(is_device)),
+           "mhd_cnn_output")
+
+
+def mhd_closure_apply(cnn: int, dt: float, state_ptr: int):
+    _check(load_library().mhd_closure_apply(ctypes.c_void_p(cnn), ctypes.c_double(dt), ctypes.c_void_p(state_ptr)),
+           "mhd_closure_apply")
+
+
+def mhd_cnn_zero_grad(cnn: int):
+    _check(load_library().mhd_cnn_zero_grad(ctypes.c_void_p(cnn)), "mhd_cnn_zero_grad")
+
+
+def mhd_cnn_accumulate(cnn: int, state_ptr: int, coarse_ptr: int, target_ptr: int, dt: float) -> float:
+    loss = ctypes.c_double(0.0)
+    _check(load_library().mhd_cnn_accumulate(ctypes.c_void_p(cnn), ctypes.c_void_p(state_ptr),
+                                             ctypes.c_void_p(coarse_ptr), ctypes.c_void_p(target_ptr),
+                                             ctypes.c_double(dt), ctypes.byref(loss)), "mhd_cnn_accumulate")
+    return loss.value
+
+
+def mhd_cnn_adam(cnn: int, lr: float, beta1: float, beta2: float, eps: float, step: int, grad_scale: float):
+    _check(load_library().mhd_cnn_adam(ctypes.c_void_p(cnn), float(lr), float(beta1), float(beta2), float(eps),
+                                       int(step), float(grad_scale)), "mhd_cnn_adam")
+
+
+def mhd_step_closure(ctx: int, cnn: int, dt: float):
+    _check(load_library().mhd_step_closure(ctypes.c_void_p(ctx), ctypes.c_void_p(cnn), ctypes.c_double(dt)),
+           "mhd_step_closure")
+
+
+def mhd_box_filter(fine_grid: MhdGrid, r: int, fine_ptr: int, coarse_ptr: int, stream_ptr: int):
+    _check(load_library().mhd_box_filter(ctypes.byref(fine_grid), int(r), ctypes.c_void_p(fine_ptr),
+                                         ctypes.c_void_p(coarse_ptr), ctypes.c_void_p(stream_ptr)),
+           "mhd_box_filter")
+
+
+def mhd_cnn_destroy(cnn: int):
+    if cnn:
+        load_library().mhd_cnn_destroy(ctypes.c_void_p(cnn))
+
+
 # ---------------------------------------------------------------------------------
 # convenience object: Mesh + Simulation in one (cf. the paper's user interface)
 # ---------------------------------------------------------------------------------
@@ -498,3 +617,81 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Closure:
+    """The learned flux-correction network on one coarse grid (device workspace owned
+    here); state arguments are device tensors of the canonical FP64 layout."""
+
+    def __init__(self, shape, length=(1.0, 1.0, 1.0), physics=None, device="cuda:0", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the MI355X path has no CPU fallback")
+        load_library()
+        self.shape = tuple(int(v) for v in shape)
+        self.grid = make_grid(shape, length)
+        self.phys = make_physics(**(physics or {}))
+        self.device = torch.device(device)
+        self.nbytes = mhd_cnn_workspace_bytes(self.grid, self.phys)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = mhd_cnn_create(self.grid, self.phys, self.workspace.data_ptr(), self.nbytes,
+                                  self.stream.cuda_stream)
+        self.nparams = mhd_cnn_param_count()
+        self.step_count = 0
+
+    def set_params(self, p):
+        mhd_cnn_set_params(self.ctx, p)
+
+    def params(self):
+        return mhd_cnn_get_params(self.ctx)
+
+    def grads(self):
+        return mhd_cnn_get_grads(self.ctx)
+
+    def set_scales(self, mu, sd, sF, sE, wU, wB):
+        mhd_cnn_set_scales(self.ctx, mu, sd, sF, sE, wU, wB)
+
+    def forward(self, state):
+        import torch
+        mhd_cnn_forward(self.ctx, state.data_ptr())
+        n = int(np.prod(self.shape))
+        out = torch.empty(18 * n, dtype=torch.float32, device=self.device)
+        mhd_cnn_output(self.ctx, out.data_ptr(), True)
+        return out
+
+    def apply(self, dt, state):
+        mhd_closure_apply(self.ctx, dt, state.data_ptr())
+
+    def zero_grad(self):
+        mhd_cnn_zero_grad(self.ctx)
+
+    def accumulate(self, state_t, coarse_next, target, dt) -> float:
+        return mhd_cnn_accumulate(self.ctx, state_t.data_ptr(), coarse_next.data_ptr(), target.data_ptr(), dt)
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, grad_scale=1.0):
+        self.step_count += 1
+        mhd_cnn_adam(self.ctx, lr, beta1, beta2, eps, self.step_count, grad_scale)
+
+    def step(self, sim, dt):
+        """One closure step of a Sim on the same grid."""
+        mhd_step_closure(sim.ctx, self.ctx, dt)
+
+    def close(self):
+        if getattr(self, "ctx", 0):
+            mhd_cnn_destroy(self.ctx)
+            self.ctx = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def box_filter(fine_shape, r, fine_state, coarse_state, stream=None):
+    """Device box filter of a fine canonical state into a coarse one (torch tensors)."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(fine_state.device)
+    mhd_box_filter(make_grid(fine_shape), r, fine_state.data_ptr(), coarse_state.data_ptr(), st.cuda_stream)

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmhd950.so")
-SOURCES = ["api.hip", "mhd_fused.hip", "dust_kernels.hip", "reduce.hip", "batch.hip"]
+SOURCES = ["api.hip", "mhd_fused.hip", "dust_kernels.hip", "reduce.hip", "batch.hip", "cnn.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -15,10 +15,10 @@ Side legs, each on its own workload and reported in its own object: the FP32-bul
 of the same run, the gas + 8 dust IMEX2P step at 192^3, and the RK2+PLM+HLLE oblique
 linear wave on a 512 x 512 x 256 box (the scheme and box of the paper's performance
 table), and 512 uneven meshblocks as one batch against the same blocks launched one by
-one.
+one, and the learned closure on held-out seeds.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--no-cpu-baseline]
-                       [--no-fp32] [--no-dust] [--no-paper-config] [--no-batch]
+                       [--no-fp32] [--no-dust] [--no-paper-config] [--no-batch] [--no-closure]
 """
 from __future__ import annotations
 
@@ -290,6 +290,35 @@ def batch_leg(nblocks: int, steps: int, warmup: int, prec: str = "fp32_bulk", se
             "tune_ms_per_pass": {str(x): [round(float(v), 4) for v in tune_ms[q]] for q, x in enumerate(classes)}}
 
 
+CLOSURE_WEIGHTS = os.path.join(ROOT, "paper_2608_14048_amd", "data", "closure_64.npz")
+
+
+def closure_leg(seeds=(900, 901), steps: int = 8):
+    """The learned closure on held-out seeds: 64^3 plain, 64^3 + closure and plain 128^3,
+    each against the 256^3 fine run filtered to 64^3 after every step (same dt
+    sequence), with the time per coarse step of each."""
+    import torch
+
+    from paper_2608_14048_amd import learned as LC
+
+    print("[bench] closure leg", file=sys.stderr, flush=True)
+    if not os.path.exists(CLOSURE_WEIGHTS):
+        return {"skipped": "no trained weights"}
+    cl, meta = LC.load(CLOSURE_WEIGHTS)
+    res, times = LC.evaluate(cl, list(seeds), meta["nc"], meta["r"], steps)
+    cl.close()
+    nc = meta["nc"]
+    summ = LC.summary(res)
+    mz = lambda ms: round(nc ** 3 / (ms * 1e-3) / 1e6, 2)
+    return {"workload": f"decaying turbulence, 64^3 coarse vs 256^3 fine filtered to 64^3, held-out seeds "
+                        f"{list(seeds)}, {steps} coarse steps, VL2+PPM+HLLD+CT FP64",
+            "l1_rel_after_steps": summ,
+            "apriori_loss_trained_vs_plain": [meta.get("heldout_trained_loss"), meta.get("heldout_zero_loss")],
+            "ms_per_coarse_step": {k: round(v, 4) for k, v in times.items()},
+            "coarse_mzcps": {"plain": mz(times["plain_ms"]), "closure": mz(times["closure_ms"]),
+                             "plain_2x": mz(times["plain_2x_ms"])}}
+
+
 def cpu_baseline(n: int, state, max_seconds: float = 30.0):
     """The oracle as it stands on a bounded sample: as many steps of the same workload
     as fit in about max_seconds (at least one)."""
@@ -352,6 +381,7 @@ def main():
     ap.add_argument("--no-paper-config", action="store_true",
                     help="skip the RK2+PLM+HLLE linear-wave leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-meshblock leg")
+    ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
     ap.add_argument("--batch-blocks", type=int, default=512)
     ap.add_argument("--dust-n", type=int, default=192)
     ap.add_argument("--paper-shape", type=int, nargs=3, default=(512, 512, 256))
@@ -438,6 +468,8 @@ def main():
                                                args.side_warmup)
     if not args.no_batch:
         out["batch"] = batch_leg(args.batch_blocks, max(args.side_steps // 5, 5), 2, "fp32_bulk", args.seed)
+    if not args.no_closure:
+        out["closure"] = closure_leg()
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(n, state, args.cpu_seconds)

@@ -15,7 +15,8 @@ Side legs, each on its own workload and reported in its own object: the FP32-bul
 of the same run, the gas + 8 dust IMEX2P step at 192^3, and the RK2+PLM+HLLE oblique
 linear wave on a 512 x 512 x 256 box (the scheme and box of the paper's performance
 table), and 512 uneven meshblocks as one batch against the same blocks launched one by
-one, and the learned closure on held-out seeds.
+one, and the learned closure on held-out seeds.  The dust leg also runs its FP32 form
+(FP32 state and explicit part, FP64 drag solve) on the same dt sequence.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--no-cpu-baseline]
                        [--no-fp32] [--no-dust] [--no-paper-config] [--no-batch] [--no-closure]
@@ -59,13 +60,21 @@ KERNEL_ALGO = {
 # u and U1 and writes u) is 5 x 36 fields; the four launches move 342 fields.
 DUST_FIELDS, DUST_MOM = 36, 27
 DUST_STEP_ALGO_BYTES = 5 * DUST_FIELDS * 8
-DUST_KERNEL_ALGO = {
-    "dust_fluid_pass_stage1": {"bytes": 2 * DUST_FIELDS * 8},              # u in, X out
-    "dust_fluid_pass_stage2": {"bytes": 3 * DUST_FIELDS * 8},              # U1, u in, X out
-    "dust_drag_stage1": {"bytes": (DUST_FIELDS + DUST_MOM) * 8},           # X in, momenta out
-    "dust_drag_cfl_stage2": {"bytes": (2 * DUST_FIELDS + DUST_MOM) * 8},   # X, U1 in, momenta out
-    "cfl": {"bytes": DUST_FIELDS * 8},
-}
+
+
+def dust_kernel_algo(word: int) -> dict:
+    """Algorithmic bytes per cell of each dust kernel class for fields of `word` bytes."""
+    return {
+        "dust_fluid_pass_stage1": {"bytes": 2 * DUST_FIELDS * word},             # u in, X out
+        "dust_fluid_pass_stage2": {"bytes": 3 * DUST_FIELDS * word},             # U1, u in, X out
+        "dust_drag_stage1": {"bytes": (DUST_FIELDS + DUST_MOM) * word},          # X in, momenta out
+        "dust_drag_cfl_stage2": {"bytes": (2 * DUST_FIELDS + DUST_MOM) * word},  # X, U1 in, momenta out
+        "cfl": {"bytes": DUST_FIELDS * 8},
+    }
+
+
+DUST_KERNEL_ALGO = dust_kernel_algo(8)
+DUST_KERNEL_ALGO_FP32 = dust_kernel_algo(4)
 
 WORKLOAD = "decaying MHD turbulence, periodic {n}^3, VL2+PPM+HLLD+CT, CFL 0.3, seed 0"
 
@@ -162,31 +171,59 @@ def kernel_roofline(times, table, ncell, workload, alu_peak=None):
     return rf
 
 
-def dust_leg(n: int, steps: int, warmup: int, seed: int = 0):
+def dust_leg(n: int, steps: int, warmup: int, seed: int = 0, fp32: bool = True):
     """Gas + 8 dust fluids, isothermal gas, IMEX2P with PLM, isothermal HLLE and
-    pressureless Rusanov, gas acceleration 0.05 x^, n^3 periodic, FP64."""
+    pressureless Rusanov, gas acceleration 0.05 x^, n^3 periodic, FP64; then (fp32) the
+    FP32 form (FP32 state and explicit part, FP64 drag solve) on the same dt sequence,
+    with the relative L1 difference of each class to the FP64 state."""
     from paper_2608_14048_amd import Sim
     from paper_2608_14048_amd import inputs as I
 
     print(f"[bench] dust leg {n}^3", file=sys.stderr, flush=True)
     state, ts = I.dust_drift(n, seed=seed)
-    sim = Sim((n, n, n), physics=dict(eos="isothermal_hydro", cs=1.0, tstop=tuple(ts),
-                                      gacc=(0.05, 0.0, 0.0)),
-              scheme=dict(recon="plm", riemann="hlle", integ="imex2p", courant=0.3))
+    physics = dict(eos="isothermal_hydro", cs=1.0, tstop=tuple(ts), gacc=(0.05, 0.0, 0.0))
+    scheme = dict(recon="plm", riemann="hlle", integ="imex2p", courant=0.3)
+    sim = Sim((n, n, n), physics=physics, scheme=scheme)
     sim.set_state(state)
-    el, times, _, _ = timed_run(sim, steps, warmup)
+    el, times, warm, dts = timed_run(sim, steps, warmup)
+    ref = sim.state(device=True) if fp32 else None
     sim.close()
     ncell = n ** 3
     value = ncell * steps / el / 1e6
-    return {"workload": f"gas + 8 dust fluids, t_s log-spaced 1e-3..10, eps 0.01 each, "
-                        f"g = 0.05, periodic {n}^3, IMEX2P+PLM+HLLE/Rusanov, CFL 0.3, seed {seed}",
-            "value": round(value, 2), "unit": "Mzone-cycles/s", "dtype": "f64", "steps": steps,
-            "ms_per_step": round(el * 1e3 / steps, 4),
-            "roofline": kernel_roofline(times, DUST_KERNEL_ALGO, ncell, f"dust{n}_fp64"),
-            "step_hbm_roofline": {"algo_bytes_per_zone_cycle": DUST_STEP_ALGO_BYTES,
-                                  "frac": round(value * 1e6 * DUST_STEP_ALGO_BYTES
-                                                / (HBM_PEAK_GBS * 1e9), 4)},
-            "kernel_ms_per_step": {k: round(v[0] / steps, 4) for k, v in sorted(times.items())}}
+    out = {"workload": f"gas + 8 dust fluids, t_s log-spaced 1e-3..10, eps 0.01 each, "
+                       f"g = 0.05, periodic {n}^3, IMEX2P+PLM+HLLE/Rusanov, CFL 0.3, seed {seed}",
+           "value": round(value, 2), "unit": "Mzone-cycles/s", "dtype": "f64", "steps": steps,
+           "ms_per_step": round(el * 1e3 / steps, 4),
+           "roofline": kernel_roofline(times, DUST_KERNEL_ALGO, ncell, f"dust{n}_fp64"),
+           "step_hbm_roofline": {"algo_bytes_per_zone_cycle": DUST_STEP_ALGO_BYTES,
+                                 "frac": round(value * 1e6 * DUST_STEP_ALGO_BYTES
+                                               / (HBM_PEAK_GBS * 1e9), 4)},
+           "kernel_ms_per_step": {k: round(v[0] / steps, 4) for k, v in sorted(times.items())}}
+    if not fp32:
+        return out
+    print("[bench] dust leg, FP32 form", file=sys.stderr, flush=True)
+    sim = Sim((n, n, n), physics=physics, scheme=dict(scheme, prec="fp32_bulk"))
+    sim.set_state(state)
+    el, times, _, _ = timed_run(sim, steps, warmup, list(warm) + list(dts))
+    nf = 4 * (len(ts) + 1)
+    got = sim.state(device=True).reshape(nf, -1)
+    sim.close()
+    ref = ref.reshape(nf, -1)
+    dust_rho = list(range(4, nf, 4))
+    rows = {"rho_gas": [0], "M_gas": [1, 2, 3], "rho_dust": dust_rho,
+            "M_dust": [r + a for r in dust_rho for a in (1, 2, 3)]}
+    l1 = {k: float((got[v] - ref[v]).abs().sum() / ref[v].abs().sum()) for k, v in rows.items()}
+    v32 = ncell * steps / el / 1e6
+    out["fp32"] = {"value": round(v32, 2), "unit": "Mzone-cycles/s",
+                   "ms_per_step": round(el * 1e3 / steps, 4), "dtype": "f32 (drag solve in f64)",
+                   "l1_rel_vs_fp64": {k: float(f"{v:.3e}") for k, v in l1.items()},
+                   "compared_after_steps": len(warm) + steps,
+                   "roofline": kernel_roofline(times, DUST_KERNEL_ALGO_FP32, ncell, f"dust{n}_fp32"),
+                   "step_hbm_roofline": {"algo_bytes_per_zone_cycle": DUST_STEP_ALGO_BYTES // 2,
+                                         "frac": round(v32 * 1e6 * (DUST_STEP_ALGO_BYTES // 2)
+                                                       / (HBM_PEAK_GBS * 1e9), 4)},
+                   "kernel_ms_per_step": {k: round(v[0] / steps, 4) for k, v in sorted(times.items())}}
+    return out
 
 
 PAPER_TABLE = {"A100 (FP64)": 300.0, "MI250X one GCD (FP64)": 250.0}
@@ -376,7 +413,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=25.0)
-    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-bulk leg")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 legs")
     ap.add_argument("--no-dust", action="store_true", help="skip the gas + dust leg")
     ap.add_argument("--no-paper-config", action="store_true",
                     help="skip the RK2+PLM+HLLE linear-wave leg")
@@ -462,7 +499,8 @@ def main():
         out["fp32_bulk"] = fp32_leg(n, state, warm_dts, dts, sim.state(device=True))
     sim.close()
     if not args.no_dust:
-        out["dust"] = dust_leg(args.dust_n, args.side_steps, args.side_warmup, args.seed)
+        out["dust"] = dust_leg(args.dust_n, args.side_steps, args.side_warmup, args.seed,
+                               fp32=not args.no_fp32)
     if not args.no_paper_config:
         out["paper_config"] = paper_config_leg(tuple(args.paper_shape), args.side_steps,
                                                args.side_warmup)

@@ -66,12 +66,16 @@ typedef enum {
 } mhd_integrator;
 typedef enum {
     MHD_PREC_FP64 = 0,     /* everything in FP64 */
-    MHD_PREC_FP32_BULK = 1 /* adiabatic MHD only: density, momenta, face fields,
+    MHD_PREC_FP32_BULK = 1 /* adiabatic MHD: density, momenta, face fields,
                               reconstruction, Riemann solves, CT and updates in FP32; the
                               total energy stored in FP64 and the pressure recovery
                               p = (gamma-1)(E - kinetic - magnetic) and the energy update
                               done in FP64; the time step and diagnostics in FP64.
-                              hlld_eps is raised to at least 1e-6. */
+                              hlld_eps is raised to at least 1e-6.
+                              Isothermal + dust: every field stored in FP32, the explicit
+                              part (primitives, reconstruction, Riemann solves, flux
+                              divergence, stage combination) in FP32; the implicit drag
+                              solve, the time step and diagnostics in FP64. */
 } mhd_precision;
 
 /* Uniform periodic grid of nx*ny*nz cells covering a box of edges length[0..2]. */
@@ -119,7 +123,7 @@ mhd_status mhd_workspace_bytes(const mhd_grid* grid, const mhd_physics* phys,
  *   adiabatic MHD     with VL2, RK2 or EULER1, any recon, HLLE or HLLD, ndust = 0,
  *                     precision FP64 or FP32_BULK;
  *   isothermal + dust with IMEX2P, DC or PLM recon, HLLE gas flux, 1 <= ndust <= 16,
- *                     precision FP64.
+ *                     precision FP64 or FP32_BULK.
  * Grids of 2^29 cells or more are MHD_E_UNSUPPORTED (fields are addressed with 32-bit
  * byte offsets).  Anything else is MHD_E_UNSUPPORTED.  The state is undefined until
  * mhd_set_state. */
@@ -132,7 +136,7 @@ mhd_status mhd_state_len(const mhd_ctx* ctx, size_t* n);
 /* Copy a canonical FP64 state in (src on the device if src_is_device, else host
  * memory; host copies complete before return).  Also computes the CFL step of the
  * new state on the device.  The FP32-bulk form rounds every field but E to FP32 here
- * (the CFL step is that of the FP64 state as given). */
+ * (every field for the dust path; the CFL step is that of the FP64 state as given). */
 mhd_status mhd_set_state(mhd_ctx* ctx, const double* src, int src_is_device);
 
 /* Copy the current state out in canonical layout; a copy to host memory completes

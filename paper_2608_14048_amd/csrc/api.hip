@@ -48,7 +48,7 @@ struct mhd_ctx {
     bool is_mhd;
     int nvar;       // fields of the canonical state
     long long n;    // cells
-    bool fp32;      // FP32-bulk form of the MHD path
+    bool fp32;      // FP32 registers: FP32-bulk MHD form, or FP32 dust (FP64 drag solve)
     // workspace views
     void* reg[3];   // state registers (MHD rotates all three; see reg_view for the layout)
     void* F;        // MHD face fluxes, 3 direction blocks (the path's real type)
@@ -109,7 +109,6 @@ mhd_status validate(const mhd_grid* g, const mhd_physics* p, const mhd_scheme* s
     if ((long long)g->nx * g->ny * g->nz >= (1LL << 29)) return MHD_E_UNSUPPORTED;
     if (!(s->courant > 0.0) || !std::isfinite(s->courant)) return MHD_E_INVAL;
     if (s->prec != MHD_PREC_FP64 && s->prec != MHD_PREC_FP32_BULK) return MHD_E_UNSUPPORTED;
-    if (s->prec == MHD_PREC_FP32_BULK && p->eos != MHD_EOS_ADIABATIC_MHD) return MHD_E_UNSUPPORTED;
     if (s->recon < MHD_RECON_DC || s->recon > MHD_RECON_PPM) return MHD_E_UNSUPPORTED;
     if (s->riemann != MHD_RS_HLLE && s->riemann != MHD_RS_HLLD) return MHD_E_UNSUPPORTED;
     if (p->eos == MHD_EOS_ADIABATIC_MHD) {
@@ -140,11 +139,14 @@ Layout layout(const mhd_grid* g, const mhd_physics* p, const mhd_scheme* sc)
     const bool fp32 = sc->prec == MHD_PREC_FP32_BULK;
     const size_t rfield = (size_t)n * (fp32 ? sizeof(float) : sizeof(double));
     Layout L;
-    L.reg = is_mhd ? align256(register_bytes(n, fp32)) : align256(field * nv);
+    L.reg = is_mhd ? align256(register_bytes(n, fp32)) : align256(rfield * nv);
     L.nreg = is_mhd ? 3 : 2;
-    // for the FP32-bulk form the flux area also stages a canonical FP64 state (8 fields);
-    // the dust path keeps no arrays besides its two registers
-    L.F = is_mhd ? align256(rfield * 21 > field * 8 ? rfield * 21 : field * 8) : 0;
+    // for the FP32 forms the flux area also stages a canonical FP64 state (nv fields);
+    // the FP64 dust path keeps no arrays besides its two registers
+    if (is_mhd)
+        L.F = align256(rfield * 21 > field * 8 ? rfield * 21 : field * 8);
+    else
+        L.F = fp32 ? align256(field * nv) : 0;
     L.Rc = is_mhd ? align256(rfield * 3) : 0;
     size_t nb = blocks_for(n);
     const size_t nf = fused_grid(make_geo(g), choose_kz(g)).nblk;
@@ -176,13 +178,25 @@ struct Tick {
     }
 };
 
+// FP32 register <-> canonical FP64 state of either path.
+hipError_t pack_reg(mhd_ctx* c, const double* canon, void* reg)
+{
+    if (c->is_mhd) return launch_pack_fp32(c->geo, canon, reg, c->stream);
+    return launch_dust_pack(c->n * c->nvar, canon, reg, c->stream);
+}
+hipError_t unpack_reg(mhd_ctx* c, const void* reg, double* canon)
+{
+    if (c->is_mhd) return launch_unpack_fp32(c->geo, reg, canon, c->stream);
+    return launch_dust_unpack(c->n * c->nvar, reg, canon, c->stream);
+}
+
 // The current state as canonical FP64 fields on the device: the register itself for the
-// FP64 form, else unpacked into the staging area.
+// FP64 forms, else unpacked into the staging area.
 const double* canonical_view(mhd_ctx* c, hipError_t* e)
 {
     *e = hipSuccess;
     if (!c->fp32) return (const double*)c->reg[c->cur];
-    *e = launch_unpack_fp32(c->geo, c->reg[c->cur], (double*)c->F, c->stream);
+    *e = unpack_reg(c, c->reg[c->cur], (double*)c->F);
     return (const double*)c->F;
 }
 
@@ -247,25 +261,26 @@ mhd_status step_mhd(mhd_ctx* c, double dt)
 // and leaves the CFL step of the new state in scalars[0].
 mhd_status step_dust(mhd_ctx* c, double dt)
 {
-    double* u = (double*)c->reg[c->cur];
-    double* U1 = (double*)c->reg[1 - c->cur];
+    void* u = c->reg[c->cur];
+    void* U1 = c->reg[1 - c->cur];
     const int recon = c->scheme.recon;
     hipError_t e;
     {
         Tick t(c, T_DUST_PASS1);
-        e = launch_fluid_pass1(c->geo, c->dp, c->dg, recon, u, U1, dt, c->stream);
+        e = launch_fluid_pass1(c->geo, c->dp, c->dg, c->fp32, recon, u, U1, dt, c->stream);
     }
     if (e == hipSuccess) {
         Tick t(c, T_DUST_DRAG1);
-        e = launch_drag1(c->geo, c->dp, U1, dt, c->stream);
+        e = launch_drag1(c->geo, c->dp, c->fp32, U1, dt, c->stream);
     }
     if (e == hipSuccess) {
         Tick t(c, T_DUST_PASS2);
-        e = launch_fluid_pass2(c->geo, c->dp, c->dg, recon, u, U1, dt, c->stream);
+        e = launch_fluid_pass2(c->geo, c->dp, c->dg, c->fp32, recon, u, U1, dt, c->stream);
     }
     if (e == hipSuccess) {
         Tick t(c, T_DUST_DRAG2);
-        e = launch_drag2_cfl(c->geo, c->dp, u, U1, dt, c->partial, c->scalars, c->cfl_scale, c->stream);
+        e = launch_drag2_cfl(c->geo, c->dp, c->fp32, u, U1, dt, c->partial, c->scalars, c->cfl_scale,
+                             c->stream);
     }
     return dev(e);
 }
@@ -368,7 +383,7 @@ mhd_status mhd_set_state(mhd_ctx* c, const double* src, int src_is_device)
     const size_t bytes = (size_t)c->n * c->nvar * sizeof(double);
     hipError_t e = hipSuccess;
     // the canonical FP64 source on the device: the register (FP64 form) or the staging
-    // area (FP32-bulk form, or a host source that must be copied first)
+    // area (FP32 forms, or a host source that must be copied first)
     const double* canon = src;
     if (!c->fp32) {
         e = hipMemcpyAsync(c->reg[c->cur], src, bytes,
@@ -380,10 +395,10 @@ mhd_status mhd_set_state(mhd_ctx* c, const double* src, int src_is_device)
     }
     if (e == hipSuccess && !src_is_device) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return MHD_E_DEVICE;
-    // the time step of the state as given, then (FP32-bulk) its packed register
+    // the time step of the state as given, then (FP32 forms) its packed register
     mhd_status st = cfl_of(c, canon);
     if (st != MHD_OK || !c->fp32) return st;
-    return dev(launch_pack_fp32(c->geo, canon, c->reg[c->cur], c->stream));
+    return dev(pack_reg(c, canon, c->reg[c->cur]));
 }
 
 mhd_status mhd_get_state(mhd_ctx* c, double* dst, int dst_is_device)
@@ -392,7 +407,7 @@ mhd_status mhd_get_state(mhd_ctx* c, double* dst, int dst_is_device)
     const size_t bytes = (size_t)c->n * c->nvar * sizeof(double);
     hipError_t e;
     if (c->fp32 && dst_is_device) {
-        e = launch_unpack_fp32(c->geo, c->reg[c->cur], dst, c->stream);
+        e = unpack_reg(c, c->reg[c->cur], dst);
         return dev(e);
     }
     const double* canon = canonical_view(c, &e);

@@ -50,9 +50,8 @@ __device__ __forceinline__ long long shifted(const Geo& g, int i, int j, int k, 
 // NaN-propagating minimum (a non-finite state must surface in the CFL reduction).
 __device__ __forceinline__ double min_nan(double a, double b)
 {
-    if (a != a) return a;
-    if (b != b) return b;
-    return a < b ? a : b;
+    const double m = a < b ? a : b;
+    return (a != a) || (b != b) ? a + b : m;  // selects, no branch
 }
 
 // Loads and stores at a 32-bit byte offset from a uniform base pointer: the address is

@@ -30,6 +30,10 @@
 //   k_drag        pointwise: adds the stage-1 drag rates (stage 2), solves S_h for the
 //                 momenta in place and, after stage 2, reduces the CFL step of the new
 //                 state (one partial per workgroup).
+//
+// Precision: templated on the stored real type R.  R = double is the FP64 form; with
+// R = float the state, the primitives, reconstruction, Riemann solves and explicit
+// updates are FP32 while the drag solve (and the CFL step) stay FP64.
 #include "launch.hpp"
 #include "physics.hpp"
 
@@ -58,13 +62,15 @@ __device__ __forceinline__ int wrap_any(int i, int n)
     return r < 0 ? r + n : r;
 }
 
-__device__ __forceinline__ double ld(const double* __restrict__ base, unsigned int idx)
+template <class T>
+__device__ __forceinline__ T ld(const T* __restrict__ base, unsigned int idx)
 {
-    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + idx * 8u);
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (unsigned int)sizeof(T));
 }
-__device__ __forceinline__ void st(double* base, unsigned int idx, double v)
+template <class T>
+__device__ __forceinline__ void st(T* base, unsigned int idx, T v)
 {
-    *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + idx * 8u) = v;
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (unsigned int)sizeof(T)) = v;
 }
 
 // a / b for finite b != 0: the hardware reciprocal refined by one Newton step, then one
@@ -77,14 +83,17 @@ __device__ __forceinline__ double div_nr(double a, double b)
     const double q = a * r;
     return fma(fma(-b, q, a), r, q);
 }
+// FP32: the hardware reciprocal (one ulp) times a
+__device__ __forceinline__ float div_nr(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
 // van Leer's harmonic-mean slope (the same formula as the shared helper, with div_nr:
 // the denominator is a sum of two numbers of one sign, never zero here).
-__device__ __forceinline__ double slope_hm(double am, double a0, double ap)
+template <class R>
+__device__ __forceinline__ R slope_hm(R am, R a0, R ap)
 {
-    const double dm = a0 - am, dp = ap - a0;
-    const double pr = dm * dp;
-    return pr > 0.0 ? div_nr(2.0 * pr, dm + dp) : 0.0;
+    const R dm = a0 - am, dp = ap - a0;
+    const R pr = dm * dp;
+    return pr > R(0) ? div_nr(R(2) * pr, dm + dp) : R(0);
 }
 
 // Halo (cells on each side) of the reconstruction when both faces of a cell are built.
@@ -95,33 +104,31 @@ struct Halo {
 
 // States on the low face (lo) and high face (hi) of the middle cell of a[0..2H]:
 // donor cell or van Leer-limited PLM, the same formula on every face.
-template <int RECON>
-__device__ __forceinline__ void both_faces(const double* a, double& loL, double& loR, double& hiL,
-                                           double& hiR)
+template <int RECON, class R>
+__device__ __forceinline__ void both_faces(const R* a, R& loL, R& loR, R& hiL, R& hiR)
 {
     if constexpr (RECON == 0) {
         loL = a[0]; loR = a[1]; hiL = a[1]; hiR = a[2];
     } else {
-        const double sm = slope_hm(a[0], a[1], a[2]);
-        const double s0 = slope_hm(a[1], a[2], a[3]);
-        const double sp = slope_hm(a[2], a[3], a[4]);
-        loL = a[1] + 0.5 * sm;
-        loR = a[2] - 0.5 * s0;
-        hiL = a[2] + 0.5 * s0;
-        hiR = a[3] - 0.5 * sp;
+        const R sm = slope_hm(a[0], a[1], a[2]);
+        const R s0 = slope_hm(a[1], a[2], a[3]);
+        const R sp = slope_hm(a[2], a[3], a[4]);
+        loL = a[1] + R(0.5) * sm;
+        loR = a[2] - R(0.5) * s0;
+        hiL = a[2] + R(0.5) * s0;
+        hiR = a[3] - R(0.5) * sp;
     }
 }
 
 // Face flux along direction D from the global-frame states; returns global-frame
 // components (mass, Mx, My, Mz).
-template <int D>
-__device__ __forceinline__ void face_flux(bool gas, double cs, const double L[4], const double R[4],
-                                          double out[4])
+template <int D, class R>
+__device__ __forceinline__ void face_flux(bool gas, R cs, const R L[4], const R Rs[4], R out[4])
 {
     constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
-    const Prim4 l{L[0], L[1 + D], L[1 + T1], L[1 + T2]};
-    const Prim4 r{R[0], R[1 + D], R[1 + T1], R[1 + T2]};
-    Flux4 f;
+    const Prim4<R> l{L[0], L[1 + D], L[1 + T1], L[1 + T2]};
+    const Prim4<R> r{Rs[0], Rs[1 + D], Rs[1 + T1], Rs[1 + T2]};
+    Flux4<R> f;
     if (gas)
         riemann_iso_hlle(l, r, cs, f);
     else
@@ -138,62 +145,63 @@ __device__ __forceinline__ void face_flux(bool gas, double cs, const double L[4]
 // explicit part of a stage, one fluid per workgroup
 // ----------------------------------------------------------------------------------
 
+template <class R>
 struct PassArgs {
-    const double* src;   // state whose fluxes are taken (u in stage 1, U1 in stage 2)
-    const double* base;  // stage 2: u (read at the own cell only); stage 1: unused
-    double* out;         // stage 1: U1; stage 2: u (in place: each cell reads then writes itself)
-    double h;            // stage 1: lam dt; stage 2: (1 - delta) dt
-    double cu, c1;       // stage 2 weights of u and U1
+    const R* src;   // state whose fluxes are taken (u in stage 1, U1 in stage 2)
+    const R* base;  // stage 2: u (read at the own cell only); stage 1: unused
+    R* out;         // stage 1: U1; stage 2: u (in place: each cell reads then writes itself)
+    double h;       // stage 1: lam dt; stage 2: (1 - delta) dt
+    double cu, c1;  // stage 2 weights of u and U1
 };
 
 // z reconstruction of one variable of one column as a pipeline over the planes the
 // column visits: push(plane m + 1 + AHEAD) returns the two states on the face m + 1/2
 // (one slope per plane for PLM).
-template <int RECON>
+template <int RECON, class R>
 struct ZLine;
-template <>
-struct ZLine<0> {
+template <class R>
+struct ZLine<0, R> {
     static constexpr int AHEAD = 0, PRIME = 1;
-    double prev;
-    __device__ void prime(const double* a) { prev = a[0]; }
-    __device__ void push(double a, double& aL, double& aR)
+    R prev;
+    __device__ void prime(const R* a) { prev = a[0]; }
+    __device__ void push(R a, R& aL, R& aR)
     {
         aL = prev;
         aR = a;
         prev = a;
     }
 };
-template <>
-struct ZLine<1> {
+template <class R>
+struct ZLine<1, R> {
     static constexpr int AHEAD = 1, PRIME = 3;
-    double am, a0, apl;  // a(m-1), a(m), high-side state of cell m-1
-    __device__ void prime(const double* a)
+    R am, a0, apl;  // a(m-1), a(m), high-side state of cell m-1
+    __device__ void prime(const R* a)
     {
-        apl = a[1] + 0.5 * slope_hm(a[0], a[1], a[2]);
+        apl = a[1] + R(0.5) * slope_hm(a[0], a[1], a[2]);
         am = a[1];
         a0 = a[2];
     }
-    __device__ void push(double a, double& aL, double& aR)
+    __device__ void push(R a, R& aL, R& aR)
     {
-        const double d = slope_hm(am, a0, a);
+        const R d = slope_hm(am, a0, a);
         aL = apl;
-        aR = a0 - 0.5 * d;
-        apl = a0 + 0.5 * d;
+        aR = a0 - R(0.5) * d;
+        apl = a0 + R(0.5) * d;
         am = a0;
         a0 = a;
     }
 };
 
-template <int RECON, int STAGE>
-__global__ __launch_bounds__(DTX* DTY) void k_fluid_pass(Geo g, DustParams p, PassArgs a, int kz,
+template <int RECON, int STAGE, class R>
+__global__ __launch_bounds__(DTX* DTY) void k_fluid_pass(Geo g, DustParams p, PassArgs<R> a, int kz,
                                                            unsigned int ntx, unsigned int nty,
                                                            unsigned int ntiles, unsigned int nblk)
 {
     constexpr int H = Halo<RECON>::H, W = 2 * H + 1;
     constexpr int LX = DTX + 2 * H, LY = DTY + 2 * H;
     constexpr int NT = DTX * DTY, NI = (LX * LY + NT - 1) / NT;  // staging items per thread
-    using Z = ZLine<RECON>;
-    __shared__ double sw[2][4][LY][LX];  // primitives of plane k (and k+1 being staged)
+    using Z = ZLine<RECON, R>;
+    __shared__ R sw[2][4][LY][LX];  // primitives of plane k (and k+1 being staged)
 
     const unsigned int item = xcd_item(blockIdx.x, nblk);
     const int s = (int)(item / ntiles);  // fluid: 0 gas, 1.. dust
@@ -209,15 +217,19 @@ __global__ __launch_bounds__(DTX* DTY) void k_fluid_pass(Geo g, DustParams p, Pa
     const int ic = live ? i : 0, jc = live ? j : 0;
     const long long n = g.n;
     const unsigned int plane = (unsigned int)g.nx * (unsigned int)g.ny;
-    const double* f[4];
-    double* o[4];
+    const R* f[4];
+    R* o[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         f[q] = a.src + (4LL * s + q) * n;
         o[q] = a.out + (4LL * s + q) * n;
     }
-    const double* b0 = a.base + 4LL * s * n;
-    const double cs = p.cs;
+    const R* b0 = a.base + 4LL * s * n;
+    const R cs = R(p.cs);
+    const R rho_floor = R(p.rho_floor), dust_floor = R(p.dust_floor);
+    const R gx3[3] = {R(p.gacc[0]), R(p.gacc[1]), R(p.gacc[2])};
+    const R hr = R(a.h), cur_ = R(a.cu), c1r = R(a.c1);
+    const R idx[3] = {R(g.inv_dx[0]), R(g.inv_dx[1]), R(g.inv_dx[2])};
     const unsigned int col = (unsigned int)jc * g.nx + ic;
 
     // this thread's staging items of a plane (tile + x/y halo, corners skipped)
@@ -236,21 +248,21 @@ __global__ __launch_bounds__(DTX* DTY) void k_fluid_pass(Geo g, DustParams p, Pa
     }
     // primitives from the raw state: the gas density is floored; a dust species below
     // its floor reads as the floor at rest
-    auto prim_of = [&](const double raw[4], double w[4]) {
-        const bool rest = !gas && raw[0] < p.dust_floor;
-        double d = raw[0];
-        if (gas && d < p.rho_floor) d = p.rho_floor;
-        const double id = 1.0 / d;
-        w[0] = rest ? p.dust_floor : d;
-        w[1] = rest ? 0.0 : raw[1] * id;
-        w[2] = rest ? 0.0 : raw[2] * id;
-        w[3] = rest ? 0.0 : raw[3] * id;
+    auto prim_of = [&](const R raw[4], R w[4]) {
+        const bool rest = !gas && raw[0] < dust_floor;
+        R d = raw[0];
+        if (gas && d < rho_floor) d = rho_floor;
+        const R id = rcp(d);
+        w[0] = rest ? dust_floor : d;
+        w[1] = rest ? R(0) : raw[1] * id;
+        w[2] = rest ? R(0) : raw[2] * id;
+        w[3] = rest ? R(0) : raw[3] * id;
     };
-    auto load_raw = [&](unsigned int c, double raw[4]) {
+    auto load_raw = [&](unsigned int c, R raw[4]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) raw[q] = ld(f[q], c);
     };
-    double raw[NI][4];
+    R raw[NI][4];
     auto fetch_plane = [&](int kk) {
         const unsigned int pb = (unsigned int)kk * plane;
 #pragma unroll
@@ -261,7 +273,7 @@ __global__ __launch_bounds__(DTX* DTY) void k_fluid_pass(Geo g, DustParams p, Pa
 #pragma unroll
         for (int m = 0; m < NI; ++m)
             if (sv[m]) {
-                double w[4];
+                R w[4];
                 prim_of(raw[m], w);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) sw[buf][v][sr[m]][sc[m]] = w[v];
@@ -271,10 +283,10 @@ __global__ __launch_bounds__(DTX* DTY) void k_fluid_pass(Geo g, DustParams p, Pa
     // z pipeline of the own column, primed so that the first push yields face k0 - 1/2
     Z zl[4];
     {
-        double pre[4][Z::PRIME];
+        R pre[4][Z::PRIME];
 #pragma unroll
         for (int m = 0; m < Z::PRIME; ++m) {
-            double r4[4], w[4];
+            R r4[4], w[4];
             load_raw((unsigned int)wrap_any(k0 - Z::PRIME + Z::AHEAD + m, g.nz) * plane + col, r4);
             prim_of(r4, w);
 #pragma unroll
@@ -283,15 +295,15 @@ __global__ __launch_bounds__(DTX* DTY) void k_fluid_pass(Geo g, DustParams p, Pa
 #pragma unroll
         for (int v = 0; v < 4; ++v) zl[v].prime(pre[v]);
     }
-    double zraw[4];  // raw state of the next plane the z pipeline takes
+    R zraw[4];  // raw state of the next plane the z pipeline takes
     load_raw((unsigned int)wrap_any(k0 + Z::AHEAD, g.nz) * plane + col, zraw);
-    double fzlo[4];  // z flux on the low face of the current cell
+    R fzlo[4];  // z flux on the low face of the current cell
     {
-        double w[4], L[4], R[4];
+        R w[4], L[4], Rr[4];
         prim_of(zraw, w);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) zl[v].push(w[v], L[v], R[v]);
-        face_flux<2>(gas, cs, L, R, fzlo);
+        for (int v = 0; v < 4; ++v) zl[v].push(w[v], L[v], Rr[v]);
+        face_flux<2>(gas, cs, L, Rr, fzlo);
     }
     load_raw((unsigned int)wrap_any(k0 + 1 + Z::AHEAD, g.nz) * plane + col, zraw);
     fetch_plane(k0);
@@ -304,60 +316,60 @@ __global__ __launch_bounds__(DTX* DTY) void k_fluid_pass(Geo g, DustParams p, Pa
         const bool more = k + 1 < k1;
         if (more) fetch_plane(k + 1);
         const unsigned int c = (unsigned int)k * plane + col;
-        double own[4], ub[4];
+        R own[4], ub[4];
         load_raw(c, own);
         if constexpr (STAGE == 2) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) ub[v] = ld(b0 + v * n, c);
         }
-        double zw[4];
+        R zw[4];
         prim_of(zraw, zw);
         if (more) load_raw((unsigned int)wrap_any(k + 2 + Z::AHEAD, g.nz) * plane + col, zraw);
 
         // acc = ((fx + fy) + fz): flux differences accumulated direction by direction
-        double acc[4];
+        R acc[4];
         {
-            double Lm[4], Rm[4], Lp[4], Rp[4], st5[W], fl[4], fh[4];
+            R Lm[4], Rm[4], Lp[4], Rp[4], st5[W], fl[4], fh[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
 #pragma unroll
                 for (int m = 0; m < W; ++m) st5[m] = sw[cur][v][row + H][lane + m];
-                both_faces<RECON>(st5, Lm[v], Rm[v], Lp[v], Rp[v]);
+                both_faces<RECON, R>(st5, Lm[v], Rm[v], Lp[v], Rp[v]);
             }
             face_flux<0>(gas, cs, Lm, Rm, fl);
             face_flux<0>(gas, cs, Lp, Rp, fh);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[v] = (fh[v] - fl[v]) * g.inv_dx[0];
+            for (int v = 0; v < 4; ++v) acc[v] = (fh[v] - fl[v]) * idx[0];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
 #pragma unroll
                 for (int m = 0; m < W; ++m) st5[m] = sw[cur][v][row + m][lane + H];
-                both_faces<RECON>(st5, Lm[v], Rm[v], Lp[v], Rp[v]);
+                both_faces<RECON, R>(st5, Lm[v], Rm[v], Lp[v], Rp[v]);
             }
             face_flux<1>(gas, cs, Lm, Rm, fl);
             face_flux<1>(gas, cs, Lp, Rp, fh);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[v] = acc[v] + (fh[v] - fl[v]) * g.inv_dx[1];
+            for (int v = 0; v < 4; ++v) acc[v] = acc[v] + (fh[v] - fl[v]) * idx[1];
 #pragma unroll
             for (int v = 0; v < 4; ++v) zl[v].push(zw[v], Lp[v], Rp[v]);
             face_flux<2>(gas, cs, Lp, Rp, fh);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                acc[v] = acc[v] + (fh[v] - fzlo[v]) * g.inv_dx[2];
+                acc[v] = acc[v] + (fh[v] - fzlo[v]) * idx[2];
                 fzlo[v] = fh[v];
             }
         }
         if (live) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                double L = -acc[v];
+                R L = -acc[v];
                 // the gas acceleration acts on the raw gas density
-                if (gas && v > 0) L += own[0] * p.gacc[v - 1];
-                double X;
+                if (gas && v > 0) L += own[0] * gx3[v - 1];
+                R X;
                 if constexpr (STAGE == 1)
-                    X = own[v] + a.h * L;
+                    X = own[v] + hr * L;
                 else
-                    X = (a.cu * ub[v] + a.c1 * own[v]) + a.h * L;
+                    X = (cur_ * ub[v] + c1r * own[v]) + hr * L;
                 st(o[v], c, X);
             }
         }
@@ -370,40 +382,57 @@ __global__ __launch_bounds__(DTX* DTY) void k_fluid_pass(Geo g, DustParams p, Pa
 // drag solve (and the CFL step after stage 2), pointwise
 // ----------------------------------------------------------------------------------
 
-// Closed-form drag solve of one momentum component, in place on mom[0..ND].
+// Constants of one drag solve S_h, computed on the host per launch (h = lam dt):
+// w_k = h/(t_k + h), a_k = t_k/(t_k + h) and 1/t_k, so that no cell divides by them.
+struct DragCoef {
+    double w[kMaxDust], a[kMaxDust], its[kMaxDust];
+    double h, cg;  // cg: weight of the stage-1 drag rates (stage 2)
+};
+
+static DragCoef drag_coef(const DustParams& p, double h, double cg)
+{
+    DragCoef q{};
+    for (int s = 0; s < p.nd; ++s) {
+        q.w[s] = h / (p.ts[s] + h);
+        q.a[s] = p.ts[s] / (p.ts[s] + h);
+        q.its[s] = 1.0 / p.ts[s];
+    }
+    q.h = h;
+    q.cg = cg;
+    return q;
+}
+
+// Closed-form drag solve of one momentum component, in place on mom[0..ND]:
+// v_g' = (p_g + sum w_k p_k)/(rho_g + sum w_k rho_k), p_k' = a_k p_k + w_k rho_k v_g'.
 template <int ND>
-__device__ __forceinline__ void drag_solve(const DustParams& p, const double* rho, double* mom,
-                                           double h)
+__device__ __forceinline__ void drag_solve(const DragCoef& q, const double* rho, double* mom)
 {
     double num = mom[0], den = rho[0];
 #pragma unroll
     for (int s = 1; s <= ND; ++s) {
-        const double w = h / (p.ts[s - 1] + h);
-        num += w * mom[s];
-        den += w * rho[s];
+        num += q.w[s - 1] * mom[s];
+        den += q.w[s - 1] * rho[s];
     }
     const double vg = num / den;
 #pragma unroll
-    for (int s = 1; s <= ND; ++s) {
-        const double t = p.ts[s - 1];
-        mom[s] = (t * mom[s] + h * rho[s] * vg) / (t + h);
-    }
+    for (int s = 1; s <= ND; ++s) mom[s] = q.a[s - 1] * mom[s] + q.w[s - 1] * (rho[s] * vg);
     mom[0] = rho[0] * vg;
 }
 
-// Velocity component a of fluid s at cell c of state U (the primitive recovery of the
-// explicit part).
-__device__ __forceinline__ double fluid_vel(const DustParams& p, const double* __restrict__ U,
-                                            long long n, int s, int a, unsigned int c)
+// Reciprocal density of fluid s for its velocity: the gas density floored; a dust
+// species below its floor is at rest (0).
+__device__ __forceinline__ double inv_density(const DustParams& p, int s, double d)
 {
-    const double* u = U + 4LL * s * n;
-    double d = ld(u, c);
-    if (s == 0) {
-        if (d < p.rho_floor) d = p.rho_floor;
-    } else if (d < p.dust_floor) {
-        return 0.0;
-    }
-    return ld(u + (1 + a) * n, c) / d;
+    const double f = s == 0 ? p.rho_floor : p.dust_floor;
+    const double iv = 1.0 / (d < f ? f : d);
+    return s > 0 && d < f ? 0.0 : iv;
+}
+
+// NaN-propagating maximum of non-negative speeds
+__device__ __forceinline__ double max_nan(double a, double b)
+{
+    const double m = a > b ? a : b;
+    return (a != a) || (b != b) ? a + b : m;
 }
 
 __device__ __forceinline__ double wave_min(double v)
@@ -415,53 +444,58 @@ __device__ __forceinline__ double wave_min(double v)
 
 // X: the explicit part (densities final); U1: stage-1 state (stage 2 only).  The number
 // of dust species ND is a template parameter so the per-cell vectors live in registers.
-template <int STAGE, int ND>
-__global__ __launch_bounds__(kBlock) void k_drag(Geo g, DustParams p, double* __restrict__ X,
-                                                 const double* __restrict__ U1, double h, double cg,
-                                                 double* __restrict__ partial)
+// Loads are of the stored type R; the solve is FP64.
+template <int STAGE, int ND, class R>
+__global__ __launch_bounds__(kBlock) void k_drag(Geo g, DustParams p, DragCoef q, R* __restrict__ X,
+                                                 const R* __restrict__ U1, double* __restrict__ partial)
 {
     const long long cl = (long long)blockIdx.x * kBlock + threadIdx.x;
     const long long n = g.n;
     double r = INFINITY;
     if (cl < n) {
         const unsigned int c = (unsigned int)cl;
-        double rho[ND + 1];
+        double rho[ND + 1], r1[ND + 1], iv1[ND + 1], ivn[ND + 1];
 #pragma unroll
-        for (int s = 0; s <= ND; ++s) rho[s] = ld(X + 4LL * s * n, c);
+        for (int s = 0; s <= ND; ++s) rho[s] = (double)ld(X + 4LL * s * n, c);
+        if constexpr (STAGE == 2) {
+#pragma unroll
+            for (int s = 0; s <= ND; ++s) {
+                r1[s] = (double)ld(U1 + 4LL * s * n, c);
+                iv1[s] = inv_density(p, s, r1[s]);
+                ivn[s] = inv_density(p, s, rho[s]);
+            }
+        }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             double mom[ND + 1];
 #pragma unroll
-            for (int s = 0; s <= ND; ++s) mom[s] = ld(X + (4LL * s + 1 + a) * n, c);
+            for (int s = 0; s <= ND; ++s) mom[s] = (double)ld(X + (4LL * s + 1 + a) * n, c);
             if constexpr (STAGE == 2) {
                 // + (1 - lam - delta) dt G(U1): drag rates of the stage-1 state
-                const double vg = fluid_vel(p, U1, n, 0, a, c);
+                const double vg = (double)ld(U1 + (1LL + a) * n, c) * iv1[0];
                 double gsum = 0.0;
 #pragma unroll
                 for (int s = 1; s <= ND; ++s) {
-                    const double fk = ld(U1 + 4LL * s * n, c) * (vg - fluid_vel(p, U1, n, s, a, c)) / p.ts[s - 1];
-                    mom[s] = mom[s] + cg * fk;
+                    const double vk = (double)ld(U1 + (4LL * s + 1 + a) * n, c) * iv1[s];
+                    const double fk = r1[s] * (vg - vk) * q.its[s - 1];
+                    mom[s] = mom[s] + q.cg * fk;
                     gsum -= fk;
                 }
-                mom[0] = mom[0] + cg * gsum;
+                mom[0] = mom[0] + q.cg * gsum;
             }
-            drag_solve<ND>(p, rho, mom, h);
+            drag_solve<ND>(q, rho, mom);
 #pragma unroll
-            for (int s = 0; s <= ND; ++s) st(X + (4LL * s + 1 + a) * n, c, mom[s]);
+            for (int s = 0; s <= ND; ++s) {
+                st(X + (4LL * s + 1 + a) * n, c, (R)mom[s]);
+                mom[s] = (double)(R)mom[s];  // the CFL step sees the stored state
+            }
             if constexpr (STAGE == 2) {
-                // time step of the new state, as the standalone CFL kernel takes it
+                // time step of the new state, as the standalone CFL kernel takes it:
+                // min_s dx/(|v_s| + c_s) = dx / max_s(|v_s| + c_s) (division is monotone)
+                double sp = fabs(mom[0] * ivn[0]) + p.cs;
 #pragma unroll
-                for (int s = 0; s <= ND; ++s) {
-                    double d = rho[s], v;
-                    if (s == 0) {
-                        if (d < p.rho_floor) d = p.rho_floor;
-                        v = mom[s] / d;
-                    } else {
-                        v = d < p.dust_floor ? 0.0 : mom[s] / d;
-                    }
-                    const double cs = s == 0 ? p.cs : 0.0;
-                    r = min_nan(r, g.dx[a] / (fabs(v) + cs));
-                }
+                for (int s = 1; s <= ND; ++s) sp = max_nan(sp, fabs(mom[s] * ivn[s]));
+                r = min_nan(r, g.dx[a] / sp);
             }
         }
     }
@@ -479,27 +513,27 @@ __global__ __launch_bounds__(kBlock) void k_drag(Geo g, DustParams p, double* __
     }
 }
 
-template <int STAGE, int ND>
-static void drag_launch(const Geo& g, const DustParams& p, double* X, const double* U1, double h,
-                        double cg, double* partial, hipStream_t s)
+template <int STAGE, int ND, class R>
+static void drag_launch(const Geo& g, const DustParams& p, const DragCoef& q, R* X, const R* U1,
+                        double* partial, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_drag<STAGE, ND>), dim3(blocks_for(g.n)), dim3(kBlock), 0, s, g, p, X, U1, h,
-                       cg, partial);
+    hipLaunchKernelGGL((k_drag<STAGE, ND, R>), dim3(blocks_for(g.n)), dim3(kBlock), 0, s, g, p, q, X, U1,
+                       partial);
 }
 
 // Dispatch on the species count (1..kMaxDust) to the specialised kernel.
-template <int STAGE, int ND = 1>
-static hipError_t drag_dispatch(const Geo& g, const DustParams& p, double* X, const double* U1, double h,
-                                double cg, double* partial, hipStream_t s)
+template <int STAGE, class R, int ND = 1>
+static hipError_t drag_dispatch(const Geo& g, const DustParams& p, const DragCoef& q, R* X, const R* U1,
+                                double* partial, hipStream_t s)
 {
     if constexpr (ND > kMaxDust) {
         return hipErrorInvalidValue;
     } else {
         if (p.nd == ND) {
-            drag_launch<STAGE, ND>(g, p, X, U1, h, cg, partial, s);
+            drag_launch<STAGE, ND, R>(g, p, q, X, U1, partial, s);
             return hipGetLastError();
         }
-        return drag_dispatch<STAGE, ND + 1>(g, p, X, U1, h, cg, partial, s);
+        return drag_dispatch<STAGE, R, ND + 1>(g, p, q, X, U1, partial, s);
     }
 }
 
@@ -523,43 +557,87 @@ DustGrid dust_grid(const Geo& g, int nfluids)
     return d;
 }
 
-template <int RECON>
-static hipError_t pass(const Geo& g, const DustParams& p, const DustGrid& d, int stage, const PassArgs& a,
+template <int RECON, class R>
+static hipError_t pass(const Geo& g, const DustParams& p, const DustGrid& d, int stage, const PassArgs<R>& a,
                        hipStream_t s)
 {
     const dim3 gr(d.nblk), bl(DTX * DTY);
     if (stage == 1)
-        hipLaunchKernelGGL((k_fluid_pass<RECON, 1>), gr, bl, 0, s, g, p, a, d.kz, d.ntx, d.nty, d.ntiles, d.nblk);
+        hipLaunchKernelGGL((k_fluid_pass<RECON, 1, R>), gr, bl, 0, s, g, p, a, d.kz, d.ntx, d.nty, d.ntiles, d.nblk);
     else
-        hipLaunchKernelGGL((k_fluid_pass<RECON, 2>), gr, bl, 0, s, g, p, a, d.kz, d.ntx, d.nty, d.ntiles, d.nblk);
+        hipLaunchKernelGGL((k_fluid_pass<RECON, 2, R>), gr, bl, 0, s, g, p, a, d.kz, d.ntx, d.nty, d.ntiles, d.nblk);
     return hipGetLastError();
 }
 
-hipError_t launch_fluid_pass1(const Geo& g, const DustParams& p, const DustGrid& d, int recon,
-                              const double* u, double* U1, double dt, hipStream_t s)
+template <class R>
+static hipError_t pass1(const Geo& g, const DustParams& p, const DustGrid& d, int recon, const void* u, void* U1,
+                        double dt, hipStream_t s)
 {
-    PassArgs a{u, nullptr, U1, kLam * dt, 0.0, 0.0};
-    return recon == 0 ? pass<0>(g, p, d, 1, a, s) : pass<1>(g, p, d, 1, a, s);
+    PassArgs<R> a{(const R*)u, nullptr, (R*)U1, kLam * dt, 0.0, 0.0};
+    return recon == 0 ? pass<0, R>(g, p, d, 1, a, s) : pass<1, R>(g, p, d, 1, a, s);
 }
 
-hipError_t launch_fluid_pass2(const Geo& g, const DustParams& p, const DustGrid& d, int recon,
-                              double* u, const double* U1, double dt, hipStream_t s)
+template <class R>
+static hipError_t pass2(const Geo& g, const DustParams& p, const DustGrid& d, int recon, void* u, const void* U1,
+                        double dt, hipStream_t s)
 {
-    PassArgs a{U1, u, u, (1.0 - kDelta) * dt, 1.0 - kDelta / kLam, kDelta / kLam};
-    return recon == 0 ? pass<0>(g, p, d, 2, a, s) : pass<1>(g, p, d, 2, a, s);
+    PassArgs<R> a{(const R*)U1, (const R*)u, (R*)u, (1.0 - kDelta) * dt, 1.0 - kDelta / kLam, kDelta / kLam};
+    return recon == 0 ? pass<0, R>(g, p, d, 2, a, s) : pass<1, R>(g, p, d, 2, a, s);
 }
 
-hipError_t launch_drag1(const Geo& g, const DustParams& p, double* U1, double dt, hipStream_t s)
+hipError_t launch_fluid_pass1(const Geo& g, const DustParams& p, const DustGrid& d, bool fp32, int recon,
+                              const void* u, void* U1, double dt, hipStream_t s)
 {
-    return drag_dispatch<1>(g, p, U1, nullptr, kLam * dt, 0.0, nullptr, s);
+    return fp32 ? pass1<float>(g, p, d, recon, u, U1, dt, s) : pass1<double>(g, p, d, recon, u, U1, dt, s);
 }
 
-hipError_t launch_drag2_cfl(const Geo& g, const DustParams& p, double* u, const double* U1, double dt,
+hipError_t launch_fluid_pass2(const Geo& g, const DustParams& p, const DustGrid& d, bool fp32, int recon,
+                              void* u, const void* U1, double dt, hipStream_t s)
+{
+    return fp32 ? pass2<float>(g, p, d, recon, u, U1, dt, s) : pass2<double>(g, p, d, recon, u, U1, dt, s);
+}
+
+hipError_t launch_drag1(const Geo& g, const DustParams& p, bool fp32, void* U1, double dt, hipStream_t s)
+{
+    const DragCoef q = drag_coef(p, kLam * dt, 0.0);
+    if (fp32) return drag_dispatch<1, float>(g, p, q, (float*)U1, nullptr, nullptr, s);
+    return drag_dispatch<1, double>(g, p, q, (double*)U1, nullptr, nullptr, s);
+}
+
+hipError_t launch_drag2_cfl(const Geo& g, const DustParams& p, bool fp32, void* u, const void* U1, double dt,
                             double* partial, double* dt_out, double cfl_scale, hipStream_t s)
 {
-    hipError_t e = drag_dispatch<2>(g, p, u, U1, kLam * dt, (1.0 - kLam - kDelta) * dt, partial, s);
+    const DragCoef q = drag_coef(p, kLam * dt, (1.0 - kLam - kDelta) * dt);
+    hipError_t e = fp32 ? drag_dispatch<2, float>(g, p, q, (float*)u, (const float*)U1, partial, s)
+                        : drag_dispatch<2, double>(g, p, q, (double*)u, (const double*)U1, partial, s);
     if (e != hipSuccess) return e;
     return launch_min_final(partial, blocks_for(g.n), cfl_scale, dt_out, s);
+}
+
+// FP32 dust register <-> canonical FP64 state (nv fields)
+__global__ __launch_bounds__(kBlock) void k_dust_pack(long long m, const double* __restrict__ canon,
+                                                      float* __restrict__ reg)
+{
+    const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (q < m) reg[q] = (float)canon[q];
+}
+__global__ __launch_bounds__(kBlock) void k_dust_unpack(long long m, const float* __restrict__ reg,
+                                                        double* __restrict__ canon)
+{
+    const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (q < m) canon[q] = reg[q];
+}
+
+hipError_t launch_dust_pack(long long m, const double* canon, void* reg, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dust_pack, dim3(blocks_for(m)), dim3(kBlock), 0, s, m, canon, (float*)reg);
+    return hipGetLastError();
+}
+
+hipError_t launch_dust_unpack(long long m, const void* reg, double* canon, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dust_unpack, dim3(blocks_for(m)), dim3(kBlock), 0, s, m, (const float*)reg, canon);
+    return hipGetLastError();
 }
 
 }  // namespace mhd

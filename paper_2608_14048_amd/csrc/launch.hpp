@@ -98,16 +98,20 @@ struct DustGrid {
 };
 DustGrid dust_grid(const Geo& g, int nfluids);
 // Explicit parts: stage 1 writes X = u + lam dt L(u) into U1; stage 2 writes
-// X = cu u + c1 U1 + (1 - delta) dt L(U1) over u in place.
-hipError_t launch_fluid_pass1(const Geo& g, const DustParams& p, const DustGrid& d, int recon,
-                              const double* u, double* U1, double dt, hipStream_t s);
-hipError_t launch_fluid_pass2(const Geo& g, const DustParams& p, const DustGrid& d, int recon,
-                              double* u, const double* U1, double dt, hipStream_t s);
+// X = cu u + c1 U1 + (1 - delta) dt L(U1) over u in place.  fp32: the registers hold
+// FP32 fields (explicit part in FP32, drag solve in FP64).
+hipError_t launch_fluid_pass1(const Geo& g, const DustParams& p, const DustGrid& d, bool fp32, int recon,
+                              const void* u, void* U1, double dt, hipStream_t s);
+hipError_t launch_fluid_pass2(const Geo& g, const DustParams& p, const DustGrid& d, bool fp32, int recon,
+                              void* u, const void* U1, double dt, hipStream_t s);
 // Drag solves in place on the explicit part; stage 2 adds the stage-1 drag rates first
 // and reduces the CFL step of the new state into dt_out (partial: ceil(n/kBlock) doubles).
-hipError_t launch_drag1(const Geo& g, const DustParams& p, double* U1, double dt, hipStream_t s);
-hipError_t launch_drag2_cfl(const Geo& g, const DustParams& p, double* u, const double* U1, double dt,
+hipError_t launch_drag1(const Geo& g, const DustParams& p, bool fp32, void* U1, double dt, hipStream_t s);
+hipError_t launch_drag2_cfl(const Geo& g, const DustParams& p, bool fp32, void* u, const void* U1, double dt,
                             double* partial, double* dt_out, double cfl_scale, hipStream_t s);
+// FP32 dust register <-> canonical FP64 state, m = nv * n values
+hipError_t launch_dust_pack(long long m, const double* canon, void* reg, hipStream_t s);
+hipError_t launch_dust_unpack(long long m, const void* reg, double* canon, hipStream_t s);
 
 inline unsigned int blocks_for(long long n) { return (unsigned int)((n + kBlock - 1) / kBlock); }
 

@@ -23,11 +23,13 @@ template <class R>
 struct Flux7 {
     R d, mn, mt1, mt2, e, bt1, bt2;
 };
+template <class R>
 struct Prim4 {
-    double d, vn, vt1, vt2;
+    R d, vn, vt1, vt2;
 };
+template <class R>
 struct Flux4 {
-    double d, mn, mt1, mt2;
+    R d, mn, mt1, mt2;
 };
 
 // ----------------------------------------------------------------------------------
@@ -343,36 +345,37 @@ __device__ __forceinline__ void riemann_hlld(const Prim7<R>& L, const Prim7<R>& 
 }
 
 // ----------------------------------------------------------------------------------
-// isothermal gas and pressureless dust (FP64)
+// isothermal gas and pressureless dust
 // ----------------------------------------------------------------------------------
 
-__device__ __forceinline__ void riemann_iso_hlle(const Prim4& L, const Prim4& R, double cs,
-                                                 Flux4& f)
+template <class R>
+__device__ __forceinline__ void riemann_iso_hlle(const Prim4<R>& L, const Prim4<R>& Rt, R cs, Flux4<R>& f)
 {
-    const double sl = fmin(L.vn, R.vn) - cs, sr = fmax(L.vn, R.vn) + cs;
-    const double bm = fmin(sl, 0.0), bp = fmax(sr, 0.0);
-    const double inv = 1.0 / (bp - bm);
-    const double c2 = cs * cs;
-    const double mL = L.d * L.vn, mR = R.d * R.vn;
-    const double UL[4] = {L.d, mL, L.d * L.vt1, L.d * L.vt2};
-    const double UR[4] = {R.d, mR, R.d * R.vt1, R.d * R.vt2};
-    const double FL[4] = {mL, mL * L.vn + c2 * L.d, mL * L.vt1, mL * L.vt2};
-    const double FR[4] = {mR, mR * R.vn + c2 * R.d, mR * R.vt1, mR * R.vt2};
-    double o[4];
+    const R sl = min_r(L.vn, Rt.vn) - cs, sr = max_r(L.vn, Rt.vn) + cs;
+    const R bm = min_r(sl, R(0)), bp = max_r(sr, R(0));
+    const R inv = rcp(bp - bm);
+    const R c2 = cs * cs;
+    const R mL = L.d * L.vn, mR = Rt.d * Rt.vn;
+    const R UL[4] = {L.d, mL, L.d * L.vt1, L.d * L.vt2};
+    const R UR[4] = {Rt.d, mR, Rt.d * Rt.vt1, Rt.d * Rt.vt2};
+    const R FL[4] = {mL, mL * L.vn + c2 * L.d, mL * L.vt1, mL * L.vt2};
+    const R FR[4] = {mR, mR * Rt.vn + c2 * Rt.d, mR * Rt.vt1, mR * Rt.vt2};
+    R o[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) o[q] = (bp * FL[q] - bm * FR[q] + bp * bm * (UR[q] - UL[q])) * inv;
     f.d = o[0]; f.mn = o[1]; f.mt1 = o[2]; f.mt2 = o[3];
 }
 
 // Pressureless Rusanov: central average minus max(|u_L|,|u_R|)/2 times the jump.
-__device__ __forceinline__ void riemann_dust(const Prim4& L, const Prim4& R, Flux4& f)
+template <class R>
+__device__ __forceinline__ void riemann_dust(const Prim4<R>& L, const Prim4<R>& Rt, Flux4<R>& f)
 {
-    const double a = fmax(fabs(L.vn), fabs(R.vn));
-    const double UL[4] = {L.d, L.d * L.vn, L.d * L.vt1, L.d * L.vt2};
-    const double UR[4] = {R.d, R.d * R.vn, R.d * R.vt1, R.d * R.vt2};
-    double o[4];
+    const R a = max_r(abs_r(L.vn), abs_r(Rt.vn));
+    const R UL[4] = {L.d, L.d * L.vn, L.d * L.vt1, L.d * L.vt2};
+    const R UR[4] = {Rt.d, Rt.d * Rt.vn, Rt.d * Rt.vt1, Rt.d * Rt.vt2};
+    R o[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) o[q] = 0.5 * (L.vn * UL[q] + R.vn * UR[q]) - 0.5 * a * (UR[q] - UL[q]);
+    for (int q = 0; q < 4; ++q) o[q] = R(0.5) * (L.vn * UL[q] + Rt.vn * UR[q]) - R(0.5) * a * (UR[q] - UL[q]);
     f.d = o[0]; f.mn = o[1]; f.mt1 = o[2]; f.mt2 = o[3];
 }
 

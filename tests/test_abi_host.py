@@ -42,6 +42,12 @@ def test_workspace_and_validation():
     g2, p2, s2 = _ws((16, 8, 8))
     assert B.mhd_workspace_bytes(g2, p2, s2) > nb
     assert B.mhd_workspace_bytes(*_ws(prec="fp32_bulk")) < nb
+    # the FP32 dust form: two FP32 registers plus an FP64 staging state of 4(1+N) fields
+    dust = dict(eos="isothermal_hydro", tstop=(1.0, 0.1), integ="imex2p", riemann="hlle")
+    nd64 = B.mhd_workspace_bytes(*_ws(**dust))
+    nd32 = B.mhd_workspace_bytes(*_ws(prec="fp32_bulk", **dust))
+    assert nd64 >= 2 * 12 * 512 * 8
+    assert nd32 >= 2 * 12 * 512 * 4 + 12 * 512 * 8
     bad = [
         dict(shape=(0, 8, 8)),
         dict(courant=0.0),
@@ -58,7 +64,6 @@ def test_workspace_and_validation():
         dict(eos="isothermal_hydro", tstop=(1.0,), integ="imex2p", riemann="hlle", recon="ppm"),
         dict(eos="isothermal_hydro", tstop=(), integ="imex2p", riemann="hlle"),
         dict(eos="isothermal_hydro", tstop=(1.0,) * 17, integ="imex2p", riemann="hlle"),
-        dict(eos="isothermal_hydro", tstop=(1.0,), integ="imex2p", riemann="hlle", prec="fp32_bulk"),
         dict(shape=(1024, 1024, 512)),                            # 2^29 cells: beyond 32-bit offsets
     ]
     for kw in unsupported:

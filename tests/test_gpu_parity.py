@@ -285,6 +285,7 @@ def test_dust_48_fifty_steps():
 # ----------------------------------------------------------------------------------
 
 def test_turbulence_256_one_step_full_size():
+    """FP64 and then the FP32-bulk form against the same oracle step."""
     st = I.turbulence(256, seed=0)
     pr = Pair((256, 256, 256), recon="ppm", riemann="hlld", integ="vl2")
     try:
@@ -297,9 +298,24 @@ def test_turbulence_256_one_step_full_size():
         assert_close(pr, got, ref, STEP_TOL, "turb256 x1")
     finally:
         pr.close()
+    pr = Pair32((256, 256, 256), recon="ppm", riemann="hlld")
+    try:
+        pr.sim.set_state(st)
+        pr.sim.step(dt)
+        got = pr.sim.state()
+        l1 = l1_rel(pr, got, ref)
+        e = class_errors(pr, got, ref)
+        _say(f"  turb256 x1 fp32-bulk: relative L1 {l1}  max-class {e}")
+        assert max(l1.values()) <= FP32_STEP_L1_TOL, l1
+        # over 1.7e7 cells a few sit where a limiter or HLLD branch decision flips
+        # between FP32 and FP64 inputs; there the two differ by more than round-off
+        assert max(e.values()) <= FP32_FLIP_TOL, e
+    finally:
+        pr.close()
 
 
 def test_dust_192_one_step_full_size():
+    """FP64 and then the FP32 form against the same oracle step."""
     st, ts = dust_problem((192, 192, 192), seed=0, nd=8, noise=1e-3)
     pr = Pair((192, 192, 192), eos="isothermal_hydro", tstop=ts, gacc=(0.05, 0, 0), recon="plm",
               riemann="hlle", integ="imex2p")
@@ -310,6 +326,13 @@ def test_dust_192_one_step_full_size():
         got = pr.sim.state()
         ref = oracle.step(pr.cfg, st, dt)
         assert_close(pr, got, ref, STEP_TOL, "dust192 x1")
+    finally:
+        pr.close()
+    pr = PairDust32((192, 192, 192), ts)
+    try:
+        pr.sim.set_state(st)
+        pr.sim.step(dt)
+        assert_close(pr, pr.sim.state(), ref, FP32_DUST_STEP_TOL, "dust192 x1 fp32")
     finally:
         pr.close()
 
@@ -413,6 +436,8 @@ def test_nonfinite_state_is_reported():
 # ----------------------------------------------------------------------------------
 
 FP32_STEP_TOL = 2e-6     # one step, per conserved class (R13 scale)
+FP32_STEP_L1_TOL = 1e-6  # one step, relative L1 per class
+FP32_FLIP_TOL = 1e-4     # one step, per class, where branch decisions may flip (large grids)
 FP32_RUN_L1_TOL = 1e-4   # 100 steps, relative L1 per class (measured 1.3e-5 .. 3.4e-5)
 
 
@@ -487,6 +512,110 @@ def test_fp32_bulk_invariants():
         assert abs(d1[0] - d0[0]) < 1e-6 * d0[0]
         assert np.all(np.abs(d1[1:4] - d0[1:4]) < 1e-6 * d0[0])
         # bitwise rerun
+        pr.sim.set_state(st)
+        pr.sim.run(3)
+        a = pr.sim.state()
+        pr.sim.set_state(st)
+        pr.sim.run(3)
+        assert np.array_equal(a, pr.sim.state())
+    finally:
+        pr.close()
+
+
+# ----------------------------------------------------------------------------------
+# FP32 dust form (FP32 state and explicit part, FP64 drag solve): errors against the
+# FP64 oracle, stated
+# ----------------------------------------------------------------------------------
+
+FP32_DUST_STEP_TOL = 2e-6     # one step, per class (R13 scale)
+FP32_DUST_RUN_L1_TOL = 2e-5   # 50 steps, relative L1 per class (measured 1.5e-6 .. 5.2e-6)
+
+
+def dust_l1_rel(pair, got, ref):
+    nf = 4 * (pair.nd + 1)
+    g = got.reshape(nf, -1)
+    r = ref.reshape(nf, -1)
+    dr = list(range(4, nf, 4))
+    rows = {"rho_gas": [0], "M_gas": [1, 2, 3], "rho_dust": dr,
+            "M_dust": [k + a for k in dr for a in (1, 2, 3)]}
+    return {k: float(np.abs(g[v] - r[v]).sum() / np.abs(r[v]).sum()) for k, v in rows.items()}
+
+
+class PairDust32(Pair):
+    def __init__(self, shape, tstop, gacc=(0.05, 0.0, 0.0), recon="plm"):
+        super().__init__(shape, eos="isothermal_hydro", tstop=tstop, gacc=gacc, recon=recon,
+                         riemann="hlle", integ="imex2p")
+        self.sim.close()
+        self.sim = B.Sim(shape, (1.0, 1.0, 1.0),
+                         physics=dict(eos="isothermal_hydro", tstop=tuple(tstop), gacc=gacc),
+                         scheme=dict(recon=recon, riemann="hlle", integ="imex2p", courant=0.3,
+                                     prec="fp32_bulk"))
+
+
+@pytest.mark.parametrize("recon,nd,shape", [("plm", 8, (24, 20, 18)), ("dc", 3, (13, 11, 7))])
+def test_fp32_dust_one_step_against_oracle(recon, nd, shape):
+    st, ts = dust_problem(shape, seed=1, nd=nd)
+    for stiff in (1.0, 1e-3):
+        pr = PairDust32(shape, ts * stiff, recon=recon)
+        try:
+            pr.sim.set_state(st)
+            # every field is rounded to FP32 once; the time step is the FP64 state's
+            assert np.array_equal(pr.sim.state(), st.astype(np.float32).astype(np.float64))
+            dt = oracle.dt_cfl(pr.cfg, st)
+            assert abs(pr.sim.dt_cfl() - dt) <= 1e-14 * dt
+            pr.sim.step(dt)
+            got = pr.sim.state()
+            ref = oracle.step(pr.cfg, st, dt)
+            e = class_errors(pr, got, ref)
+            _say(f"  fp32 dust {recon} nd={nd} t_s x{stiff:g}: worst {max(e.values()):.3e}  "
+                 f"L1 {dust_l1_rel(pr, got, ref)}")
+            assert np.all(np.isfinite(got))
+            assert max(e.values()) <= FP32_DUST_STEP_TOL, e
+            # the next time step is taken from the new FP32 state in FP64
+            d32 = oracle.dt_cfl(pr.cfg, got)
+            assert abs(pr.sim.dt_cfl() - d32) <= 1e-13 * d32
+        finally:
+            pr.close()
+
+
+def test_fp32_dust_48_fifty_steps_l1_against_oracle():
+    """Gas + 8 dust species recipe at 48^3, IMEX2P + PLM, 50 steps on the oracle's dt
+    sequence: relative L1 error of each class against the FP64 oracle."""
+    st, ts = dust_problem((48, 48, 48), seed=0, nd=8, noise=1e-3)
+    pr = PairDust32((48, 48, 48), ts)
+    try:
+        ref, got = run_both(pr, st, 50, check_dt=False)
+        e = dust_l1_rel(pr, got, ref)
+        _say(f"  fp32 dust48 x50: relative L1 {e}  max-class worst "
+             f"{max(class_errors(pr, got, ref).values()):.3e}")
+        assert max(e.values()) <= FP32_DUST_RUN_L1_TOL, e
+    finally:
+        pr.close()
+
+
+def test_fp32_dust_invariants():
+    """No gas acceleration: every species' mass and the total momentum stay what they
+    were, up to FP32 rounding of the stored state; reruns are bitwise equal."""
+    shape = (32, 32, 32)
+    st, ts = dust_problem(shape, seed=3, nd=8, noise=1e-2)
+    pr = PairDust32(shape, ts, gacc=(0.0, 0.0, 0.0))
+    try:
+        pr.sim.set_state(st)
+        d0 = pr.sim.diagnostics()
+        pr.sim.run(20)
+        d1 = pr.sim.diagnostics()
+        nd = 8
+        mass0 = np.concatenate([[d0[0]], d0[9:9 + nd]])
+        mass1 = np.concatenate([[d1[0]], d1[9:9 + nd]])
+        ptot0, ptot1 = d0[9 + nd:12 + nd], d1[9 + nd:12 + nd]
+        mtot = mass0.sum()
+        _say(f"  fp32 dust masses rel {np.abs(mass1 - mass0) / mass0}; "
+             f"total momentum {ptot0} -> {ptot1}")
+        assert np.all(np.abs(mass1 - mass0) <= 1e-6 * mass0)
+        # rounding of the stored momenta to FP32: far below 1e-6 of mass x peak speed
+        u = st.reshape(4 * (nd + 1), -1)
+        vmax = max(float(np.abs(u[4 * k + 1:4 * k + 4] / u[4 * k]).max()) for k in range(nd + 1))
+        assert np.all(np.abs(ptot1 - ptot0) <= 1e-6 * mtot * vmax)
         pr.sim.set_state(st)
         pr.sim.run(3)
         a = pr.sim.state()

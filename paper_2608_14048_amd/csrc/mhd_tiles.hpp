@@ -393,22 +393,6 @@ struct CtTile {
             return (unsigned int)z * plane + (unsigned int)y * nx + (unsigned int)x;
         };
         // E_x at (x, y-1/2, z-1/2), E_y at (x-1/2, y, z-1/2), E_z at (x-1/2, y-1/2, z)
-        auto edge_x = [&](int x, int y, int z) -> R {
-            const int ym = wrap_once(y - 1, g.ny), zm = wrap_once(z - 1, g.nz);
-            const unsigned int c = at(x, y, z), cy = at(x, ym, z), cz = at(x, y, zm), cyz = at(x, ym, zm);
-            // p = y, q = z: X on y-faces (slot 6 of the y sweep), Y on z-faces (slot 5 of z)
-            return gs_edge(ldT(Fb[13], c), ldT(Fb[13], cz), ldT(Fb[19], c), ldT(Fb[19], cy),
-                           ldT(Rx, c), ldT(Rx, cy), ldT(Rx, cz), ldT(Rx, cyz),
-                           ldT(Fb[7], c), ldT(Fb[7], cz), ldT(Fb[14], c), ldT(Fb[14], cy));
-        };
-        auto edge_y = [&](int x, int y, int z) -> R {
-            const int xm = wrap_once(x - 1, g.nx), zm = wrap_once(z - 1, g.nz);
-            const unsigned int c = at(x, y, z), cx = at(xm, y, z), cz = at(x, y, zm), cxz = at(xm, y, zm);
-            // p = z, q = x: X on z-faces (slot 6 of z), Y on x-faces (slot 5 of x)
-            return gs_edge(ldT(Fb[20], c), ldT(Fb[20], cx), ldT(Fb[5], c), ldT(Fb[5], cz),
-                           ldT(Ry, c), ldT(Ry, cz), ldT(Ry, cx), ldT(Ry, cxz),
-                           ldT(Fb[14], c), ldT(Fb[14], cx), ldT(Fb[0], c), ldT(Fb[0], cz));
-        };
         auto edge_z = [&](int x, int y, int z) -> R {
             const int xm = wrap_once(x - 1, g.nx), ym = wrap_once(y - 1, g.ny);
             const unsigned int c = at(x, y, z), cx = at(xm, y, z), cy = at(x, ym, z), cxy = at(xm, ym, z);
@@ -417,22 +401,83 @@ struct CtTile {
                            ldT(Rz, c), ldT(Rz, cx), ldT(Rz, cy), ldT(Rz, cxy),
                            ldT(Fb[0], c), ldT(Fb[0], cy), ldT(Fb[7], c), ldT(Fb[7], cx));
         };
-        // level edges E_x, E_y at z-level zl - 1/2 for the tile (+1 ring on the high side)
-        auto fill_level = [&](int slot, int zl) {
-            const int zz = wrap_once(zl, g.nz);
-            for (int q = threadIdx.x; q < (TX + 1) * (TY + 1); q += TX * TY) {
+        // Level edges E_x, E_y at z-level zl - 1/2 for the tile (+1 ring on the high side).
+        // A thread keeps the same edge positions on every level, so the values of plane
+        // zl - 1 that a level needs are the plane-zl values the level below read: they
+        // stay in registers (cx*, cy*) instead of coming back from memory, for the
+        // first NC edge positions of the thread.  Likewise the z fluxes of the high face
+        // (fzc) and, with CFL, the updated B_z of the high face (b3c) carry over to the
+        // plane above.  The FP64 kernel that also reduces the time step carries nothing:
+        // the extra registers would cost it half its occupancy, which it needs more.
+        constexpr int NT = TX * TY, NE = (TX + 1) * (TY + 1), NQ = (NE + NT - 1) / NT;
+        constexpr bool ZC = !(CFL && sizeof(R) == 8);
+        constexpr int NC = !ZC ? 0 : (sizeof(R) == 4 ? NQ : 1);
+        constexpr int NA = NC > 0 ? NC : 1;
+        R cx13[NA], cx7[NA], crx0[NA], crxm[NA], cy5[NA], cy0[NA], cry0[NA], cryx[NA];
+    #pragma unroll
+        for (int m = 0; m < NA; ++m) {
+            cx13[m] = cx7[m] = crx0[m] = crxm[m] = R(0);
+            cy5[m] = cy0[m] = cry0[m] = cryx[m] = R(0);
+        }
+        auto fill_level = [&](int slot, int zl, bool first) {
+            const int zz = wrap_once(zl, g.nz), zm = wrap_once(zl - 1, g.nz);
+    #pragma unroll
+            for (int m = 0; m < NQ; ++m) {
+                const int q = (int)threadIdx.x + m * NT;
                 const int r = q / (TX + 1), cc = q - r * (TX + 1);
                 const int gx = x0 + cc, gy = y0 + r;
-                if (gx > g.nx || gy > g.ny) continue;
+                if (q >= NE || gx > g.nx || gy > g.ny) continue;
                 const int wx = gx == g.nx ? 0 : gx, wy = gy == g.ny ? 0 : gy;
-                if (cc < TX && gx < g.nx) sEx[slot][r][cc] = edge_x(wx, wy, zz);
-                if (r < TY && gy < g.ny) sEy[slot][r][cc] = edge_y(wx, wy, zz);
+                if (cc < TX && gx < g.nx) {
+                    // E_x at (x, y-1/2, z-1/2); p = y, q = z: X on y-faces (slot 6 of the
+                    // y sweep), Y on z-faces (slot 5 of z)
+                    const int ym = wrap_once(wy - 1, g.ny);
+                    const unsigned int c = at(wx, wy, zz), cy = at(wx, ym, zz);
+                    const int mc = m < NA ? m : 0;
+                    R Xm = cx13[mc], R0m = crx0[mc], Rmm = crxm[mc], fpm = cx7[mc];  // plane zl - 1
+                    if (first || m >= NC) {
+                        const unsigned int cz = at(wx, wy, zm), cyz = at(wx, ym, zm);
+                        Xm = ldT(Fb[13], cz); R0m = ldT(Rx, cz);
+                        Rmm = ldT(Rx, cyz); fpm = ldT(Fb[7], cz);
+                    }
+                    const R X0 = ldT(Fb[13], c), R00 = ldT(Rx, c), Rm0 = ldT(Rx, cy), fp0 = ldT(Fb[7], c);
+                    sEx[slot][r][cc] = gs_edge(X0, Xm, ldT(Fb[19], c), ldT(Fb[19], cy), R00, Rm0, R0m, Rmm, fp0,
+                                               fpm, ldT(Fb[14], c), ldT(Fb[14], cy));
+                    if (m < NC) {
+                        cx13[mc] = X0; crx0[mc] = R00; crxm[mc] = Rm0; cx7[mc] = fp0;
+                    }
+                }
+                if (r < TY && gy < g.ny) {
+                    // E_y at (x-1/2, y, z-1/2); p = z, q = x: X on z-faces (slot 6 of z),
+                    // Y on x-faces (slot 5 of x)
+                    const int xm = wrap_once(wx - 1, g.nx);
+                    const unsigned int c = at(wx, wy, zz), cx = at(xm, wy, zz);
+                    const int mc = m < NA ? m : 0;
+                    R Ym = cy5[mc], Rm0 = cry0[mc], Rmm = cryx[mc], fqm = cy0[mc];  // plane zl - 1
+                    if (first || m >= NC) {
+                        const unsigned int cz = at(wx, wy, zm), cxz = at(xm, wy, zm);
+                        Ym = ldT(Fb[5], cz); Rm0 = ldT(Ry, cz);
+                        Rmm = ldT(Ry, cxz); fqm = ldT(Fb[0], cz);
+                    }
+                    const R Y0 = ldT(Fb[5], c), R00 = ldT(Ry, c), R0m = ldT(Ry, cx), fq0 = ldT(Fb[0], c);
+                    sEy[slot][r][cc] = gs_edge(ldT(Fb[20], c), ldT(Fb[20], cx), Y0, Ym, R00, Rm0, R0m, Rmm,
+                                               ldT(Fb[14], c), ldT(Fb[14], cx), fq0, fqm);
+                    if (m < NC) {
+                        cy5[mc] = Y0; cry0[mc] = R00; cryx[mc] = R0m; cy0[mc] = fq0;
+                    }
+                }
             }
         };
 
         double vmin = INFINITY;
         int lv = 0;
-        fill_level(lv ^ 1, k0);  // level k0 - 1/2
+        fill_level(lv ^ 1, k0, true);  // level k0 - 1/2
+        // z fluxes on the low face of the current plane (the high face of the plane below)
+        R fzc[5];
+    #pragma unroll
+        for (int v = 0; v < 5; ++v) fzc[v] = live && ZC ? ldT(Fb[14 + v], at(i, j, k0)) : R(0);
+        R b3c = R(0);  // CFL: the updated B_z on the low face, from the plane below
+        bool have_b3 = false;
         const double bdt = a.co.bdt, g0 = a.co.g0, g1 = a.co.g1;
         const R bdtr = R(bdt), g0r = R(g0), g1r = R(g1);
         const R idx = R(g.inv_dx[0]), idy = R(g.inv_dx[1]), idz = R(g.inv_dx[2]);
@@ -446,7 +491,7 @@ struct CtTile {
                 const int wx = gx == g.nx ? 0 : gx, wy = gy == g.ny ? 0 : gy;
                 sEz[r][cc] = edge_z(wx, wy, k);
             }
-            fill_level(lv, k + 1);
+            fill_level(lv, k + 1, false);
             __syncthreads();
 
             if (live) {
@@ -457,17 +502,23 @@ struct CtTile {
                 R L[4];
     #pragma unroll
                 for (int v = 0; v < 4; ++v) {
+                    const R fzh = ldT(Fb[14 + v], cz);
+                    if (!ZC) fzc[v] = ldT(Fb[14 + v], c);
                     const R fx = (ldT(Fb[v], cx) - ldT(Fb[v], c)) * idx;
                     const R fy = (ldT(Fb[7 + v], cy) - ldT(Fb[7 + v], c)) * idy;
-                    const R fz = (ldT(Fb[14 + v], cz) - ldT(Fb[14 + v], c)) * idz;
+                    const R fz = (fzh - fzc[v]) * idz;
                     L[v] = -((fx + fy) + fz);
+                    fzc[v] = fzh;
                 }
                 double LE;
                 {
+                    const R fzh = ldT(Fb[18], cz);
+                    if (!ZC) fzc[4] = ldT(Fb[18], c);
                     const double fx = ((double)ldT(Fb[4], cx) - (double)ldT(Fb[4], c)) * g.inv_dx[0];
                     const double fy = ((double)ldT(Fb[11], cy) - (double)ldT(Fb[11], c)) * g.inv_dx[1];
-                    const double fz = ((double)ldT(Fb[18], cz) - (double)ldT(Fb[18], c)) * g.inv_dx[2];
+                    const double fz = ((double)fzh - (double)fzc[4]) * g.inv_dx[2];
                     LE = -((fx + fy) + fz);
+                    fzc[4] = fzh;
                 }
                 R o[4];
                 double oE;
@@ -510,12 +561,14 @@ struct CtTile {
                 };
                 const R b1 = nb1(lane, c);
                 const R b2 = nb2(row, c);
-                const R b3 = nb3(ol, c);
+                const R b3 = CFL && ZC && have_b3 ? b3c : nb3(ol, c);
                 if (CFL) {
                     // the updated faces on the high side give the new B_cc of this cell (FP64)
+                    b3c = nb3(nl, cz);  // also the low face of the plane above
+                    have_b3 = true;
                     const double bx = 0.5 * ((double)b1 + (double)nb1(lane + 1, cx));
                     const double by = 0.5 * ((double)b2 + (double)nb2(row + 1, cy));
-                    const double bz = 0.5 * ((double)b3 + (double)nb3(nl, cz));
+                    const double bz = 0.5 * ((double)b3 + (double)b3c);
                     double d = o[0];
                     if (d < P.rho_floor) d = P.rho_floor;
                     const double id = 1.0 / d;

@@ -38,7 +38,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (an FMA counts 2)
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, packed (the kernels here issue no packed FP32)
 STEP_ALGO_BYTES = 320.0         # bytes per zone-cycle a fully fused VL2 FP64 step must move
+STEP_ALGO_BYTES_FP32 = 180.0    # the same for the FP32-bulk form (7 FP32 fields + FP64 E)
 
 # Algorithmic work per cell of one launch of each kernel class.  Bytes: every array the
 # kernel needs read once, every array it produces written once (FP64).  Flops: the
@@ -52,6 +54,16 @@ KERNEL_ALGO = {
     "mhd_ct_update_corrector": {"bytes": (24 + 8 + 8) * 8, "flops": 192},
     "mhd_ct_update_predictor": {"bytes": (24 + 8 + 8) * 8, "flops": 120},
     "cfl": {"bytes": 8 * 8, "flops": 72},
+}
+
+# FP32-bulk form: a state is 7 FP32 fields + FP64 E = 36 B, a face or cell-E field 4 B;
+# the flops are those of the FP64 table, in FP32 (E's update in FP64)
+KERNEL_ALGO_FP32 = {
+    "mhd_flux_corrector": {"bytes": 36 + 24 * 4, "flops": 1701},
+    "mhd_flux_predictor": {"bytes": 36 + 24 * 4, "flops": 1155},
+    "mhd_ct_update_corrector": {"bytes": 24 * 4 + 36 + 36, "flops": 192},
+    "mhd_ct_update_predictor": {"bytes": 24 * 4 + 36 + 36, "flops": 120},
+    "cfl": {"bytes": 36, "flops": 72},
 }
 
 # Gas + dust IMEX2P kernels (36 fields per state at 8 dust species, 27 of them momenta),
@@ -397,10 +409,15 @@ def fp32_leg(n, state, warm_dts, dts, ref64):
     l1 = {k: float((got[v] - ref[v]).abs().sum() / ref[v].abs().sum()) for k, v in rows.items()}
     sim.close()
     steps = len(dts)
-    return {"value": round(n ** 3 * steps / el / 1e6, 2), "unit": "Mzone-cycles/s",
+    value = n ** 3 * steps / el / 1e6
+    return {"value": round(value, 2), "unit": "Mzone-cycles/s",
             "ms_per_step": round(el * 1e3 / steps, 4), "dtype": "f32 (E in f64)",
             "l1_rel_vs_fp64": {k: float(f"{v:.3e}") for k, v in l1.items()},
             "compared_after_steps": len(warm_dts) + steps,
+            "roofline": kernel_roofline(times, KERNEL_ALGO_FP32, n ** 3, f"turb{n}_fp32_bulk",
+                                        FP32_VECTOR_PEAK_TFLOPS),
+            "step_hbm_roofline": {"algo_bytes_per_zone_cycle": STEP_ALGO_BYTES_FP32,
+                                  "frac": round(value * 1e6 * STEP_ALGO_BYTES_FP32 / (HBM_PEAK_GBS * 1e9), 4)},
             "kernel_ms_per_step": {k: round(v[0] / steps, 4) for k, v in sorted(times.items())}}
 
 

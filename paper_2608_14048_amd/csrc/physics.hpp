@@ -243,6 +243,47 @@ __device__ __forceinline__ void riemann_hlle(const Prim7<R>& L, const Prim7<R>& 
     to_flux(o, f);
 }
 
+// What the HLLD wave speeds and star states need of one face-frame state: total
+// pressure, v.B, total energy and the fast speed (the conserved vector and the flux are
+// built later for the one side the face's region needs).
+template <class R>
+struct Lite {
+    R pt, vb, e, cf;
+};
+
+template <class R>
+__device__ __forceinline__ void lite_of(const Prim7<R>& w, R bn, R gam, R gm1inv, Lite<R>& s)
+{
+    const R bt2 = w.bt1 * w.bt1 + w.bt2 * w.bt2;
+    const R b2 = bn * bn + bt2;
+    const R v2 = w.vn * w.vn + (w.vt1 * w.vt1 + w.vt2 * w.vt2);
+    s.pt = w.p + R(0.5) * b2;
+    s.e = w.p * gm1inv + R(0.5) * w.d * v2 + R(0.5) * b2;
+    s.vb = w.vn * bn + (w.vt1 * w.bt1 + w.vt2 * w.bt2);
+    s.cf = fast_speed(gam, w.d, w.p, b2, bn);
+}
+
+// Conserved vector and physical flux of one state (the formulas of side_of).
+template <class R>
+__device__ __forceinline__ void uf_of(const Prim7<R>& w, const Lite<R>& s, R bn, R U[7], R F[7])
+{
+    const R mn = w.d * w.vn;
+    U[0] = w.d;
+    U[1] = mn;
+    U[2] = w.d * w.vt1;
+    U[3] = w.d * w.vt2;
+    U[4] = s.e;
+    U[5] = w.bt1;
+    U[6] = w.bt2;
+    F[0] = mn;
+    F[1] = mn * w.vn + s.pt - bn * bn;
+    F[2] = mn * w.vt1 - bn * w.bt1;
+    F[3] = mn * w.vt2 - bn * w.bt2;
+    F[4] = (s.e + s.pt) * w.vn - bn * s.vb;
+    F[5] = w.bt1 * w.vn - bn * w.vt1;
+    F[6] = w.bt2 * w.vn - bn * w.vt2;
+}
+
 // One side of the HLLD star region: density behind the fast wave, transverse velocity
 // and field from the jump conditions (kept at their outer values where the
 // denominator degenerates), and the energy from the energy jump condition.
@@ -252,7 +293,7 @@ struct Star {
 };
 
 template <class R>
-__device__ __forceinline__ void star_of(const Prim7<R>& w, const Side<R>& s, R bn, R S, R SM, R pts,
+__device__ __forceinline__ void star_of(const Prim7<R>& w, const Lite<R>& s, R bn, R S, R SM, R pts,
                                         R eps, Star<R>& o)
 {
     const R du = S - w.vn;
@@ -271,76 +312,87 @@ __device__ __forceinline__ void star_of(const Prim7<R>& w, const Side<R>& s, R b
         o.bt2 = w.bt2 * cb;
     }
     o.vb = SM * bn + (o.vt1 * o.bt1 + o.vt2 * o.bt2);
-    o.e = (du * s.U[4] - s.pt * w.vn + pts * SM + bn * (s.vb - o.vb)) * ds;
+    o.e = (du * s.e - s.pt * w.vn + pts * SM + bn * (s.vb - o.vb)) * ds;
     o.sqd = sqrt_r(o.d);
 }
 
-// Miyoshi & Kusano (2005) five-wave HLLD flux.
+// Miyoshi & Kusano (2005) five-wave HLLD flux.  Every region's flux has the form
+// F(W) + S (U_a - U(W)) + S_a (U_b - U_a) for one outer state W: F(W) in the
+// supersonic regions (S = S_a = 0), F(W) + S (U* - U(W)) in the outer star regions,
+// and the full form between the Alfven waves, W on the side of the contact.  The
+// conserved vector and flux are built once, for that W.
 template <class R>
 __device__ __forceinline__ void riemann_hlld(const Prim7<R>& L, const Prim7<R>& Rt, R bn, R gam,
                                              R gm1inv, R eps, Flux7<R>& f)
 {
-    Side<R> a, b;
-    side_of(L, bn, gam, gm1inv, a);
-    side_of(Rt, bn, gam, gm1inv, b);
+    Lite<R> a, b;
+    lite_of(L, bn, gam, gm1inv, a);
+    lite_of(Rt, bn, gam, gm1inv, b);
     const R cmax = max_r(a.cf, b.cf);
     const R sl = min_r(L.vn, Rt.vn) - cmax;
     const R sr = max_r(L.vn, Rt.vn) + cmax;
-    if (sl > R(0)) { to_flux(a.F, f); return; }
-    if (sr < R(0)) { to_flux(b.F, f); return; }
 
-    const R ml = L.d * (sl - L.vn), mr = Rt.d * (sr - Rt.vn);  // mass fluxes into the fan
-    const R iden = rcp(mr - ml);
-    const R SM = (mr * Rt.vn - ml * L.vn - b.pt + a.pt) * iden;
-    const R pts = (mr * a.pt - ml * b.pt + ml * mr * (Rt.vn - L.vn)) * iden;
+    const bool sup = sl > R(0) || sr < R(0);
+    bool useL = sl > R(0);
+    R S = R(0), Sa = R(0);
+    R ua[7], ub[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) ua[q] = ub[q] = R(0);
+    if (!sup) {
+        const R ml = L.d * (sl - L.vn), mr = Rt.d * (sr - Rt.vn);  // mass fluxes into the fan
+        const R iden = rcp(mr - ml);
+        const R SM = (mr * Rt.vn - ml * L.vn - b.pt + a.pt) * iden;
+        const R pts = (mr * a.pt - ml * b.pt + ml * mr * (Rt.vn - L.vn)) * iden;
 
-    Star<R> x, y;
-    star_of(L, a, bn, sl, SM, pts, eps, x);
-    star_of(Rt, b, bn, sr, SM, pts, eps, y);
-    const R slst = SM - div_r(abs_r(bn), x.sqd);
-    const R srst = SM + div_r(abs_r(bn), y.sqd);
-
-    // U* on each side
-    R ul[7] = {x.d, x.d * SM, x.d * x.vt1, x.d * x.vt2, x.e, x.bt1, x.bt2};
-    R ur[7] = {y.d, y.d * SM, y.d * y.vt1, y.d * y.vt2, y.e, y.bt1, y.bt2};
+        Star<R> x, y;
+        star_of(L, a, bn, sl, SM, pts, eps, x);
+        star_of(Rt, b, bn, sr, SM, pts, eps, y);
+        const R slst = SM - div_r(abs_r(bn), x.sqd);
+        const R srst = SM + div_r(abs_r(bn), y.sqd);
+        const bool outerL = slst >= R(0), outerR = !outerL && srst < R(0);
+        const bool left = outerL || (!outerR && SM >= R(0));
+        useL = left;
+        // U* of the side of W
+        const Star<R>& st = left ? x : y;
+        ua[0] = st.d; ua[1] = st.d * SM; ua[2] = st.d * st.vt1; ua[3] = st.d * st.vt2;
+        ua[4] = st.e; ua[5] = st.bt1; ua[6] = st.bt2;
+        S = left ? sl : sr;
+        if (!outerL && !outerR) {
+            // between the two Alfven waves: U** of the side of W
+            Sa = left ? slst : srst;
+            if (bn * bn <= eps * pts) {
+#pragma unroll
+                for (int q = 0; q < 7; ++q) ub[q] = ua[q];
+            } else {
+                const R sg = bn > R(0) ? R(1) : R(-1);
+                const R inv = rcp(x.sqd + y.sqd);
+                const R v1 = (x.sqd * x.vt1 + y.sqd * y.vt1 + (y.bt1 - x.bt1) * sg) * inv;
+                const R v2 = (x.sqd * x.vt2 + y.sqd * y.vt2 + (y.bt2 - x.bt2) * sg) * inv;
+                const R b1 = (x.sqd * y.bt1 + y.sqd * x.bt1 + x.sqd * y.sqd * (y.vt1 - x.vt1) * sg) * inv;
+                const R b2 = (x.sqd * y.bt2 + y.sqd * x.bt2 + x.sqd * y.sqd * (y.vt2 - x.vt2) * sg) * inv;
+                const R vbss = SM * bn + (v1 * b1 + v2 * b2);
+                const R ess = left ? x.e - x.sqd * (x.vb - vbss) * sg : y.e + y.sqd * (y.vb - vbss) * sg;
+                ub[0] = st.d; ub[1] = st.d * SM; ub[2] = st.d * v1; ub[3] = st.d * v2;
+                ub[4] = ess; ub[5] = b1; ub[6] = b2;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 7; ++q) ub[q] = ua[q];
+        }
+    }
+    // the outer state W and its conserved vector and flux
+    const Prim7<R>& w = useL ? L : Rt;
+    const Lite<R>& sw = useL ? a : b;
+    R U[7], F[7];
+    uf_of(w, sw, bn, U, F);
+    if (sup) {
+        // supersonic: F(W) exactly
+#pragma unroll
+        for (int q = 0; q < 7; ++q) ua[q] = ub[q] = U[q];
+    }
     R o[7];
-    if (slst >= R(0)) {
 #pragma unroll
-        for (int q = 0; q < 7; ++q) o[q] = a.F[q] + sl * (ul[q] - a.U[q]);
-        to_flux(o, f);
-        return;
-    }
-    if (srst < R(0)) {
-#pragma unroll
-        for (int q = 0; q < 7; ++q) o[q] = b.F[q] + sr * (ur[q] - b.U[q]);
-        to_flux(o, f);
-        return;
-    }
-    // between the two Alfven waves
-    const bool left = SM >= R(0);
-    const Star<R>& st = left ? x : y;
-    const R* us = left ? ul : ur;
-    const R S = left ? sl : sr;
-    const R Sst = left ? slst : srst;
-    const Side<R>& sd = left ? a : b;
-    R uss[7];
-    if (bn * bn <= eps * pts) {
-#pragma unroll
-        for (int q = 0; q < 7; ++q) uss[q] = us[q];
-    } else {
-        const R sg = bn > R(0) ? R(1) : R(-1);
-        const R inv = rcp(x.sqd + y.sqd);
-        const R v1 = (x.sqd * x.vt1 + y.sqd * y.vt1 + (y.bt1 - x.bt1) * sg) * inv;
-        const R v2 = (x.sqd * x.vt2 + y.sqd * y.vt2 + (y.bt2 - x.bt2) * sg) * inv;
-        const R b1 = (x.sqd * y.bt1 + y.sqd * x.bt1 + x.sqd * y.sqd * (y.vt1 - x.vt1) * sg) * inv;
-        const R b2 = (x.sqd * y.bt2 + y.sqd * x.bt2 + x.sqd * y.sqd * (y.vt2 - x.vt2) * sg) * inv;
-        const R vbss = SM * bn + (v1 * b1 + v2 * b2);
-        const R ess = left ? x.e - x.sqd * (x.vb - vbss) * sg : y.e + y.sqd * (y.vb - vbss) * sg;
-        uss[0] = st.d; uss[1] = st.d * SM; uss[2] = st.d * v1; uss[3] = st.d * v2;
-        uss[4] = ess; uss[5] = b1; uss[6] = b2;
-    }
-#pragma unroll
-    for (int q = 0; q < 7; ++q) o[q] = sd.F[q] + S * (us[q] - sd.U[q]) + Sst * (uss[q] - us[q]);
+    for (int q = 0; q < 7; ++q) o[q] = F[q] + S * (ua[q] - U[q]) + Sa * (ub[q] - ua[q]);
     to_flux(o, f);
 }
 

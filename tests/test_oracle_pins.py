@@ -597,6 +597,40 @@ def test_drag_relaxation_matches_matrix_exponential_second_order():
     assert abs(abar - g["abar_printed"][0]) < 0.005
 
 
+def test_two_fluid_relative_velocity_decays_exponentially():
+    """One dust species, no forcing: the drag system v_g' = eps (v_d - v_g)/t_s,
+    v_d' = (v_g - v_d)/t_s gives dv(t) = dv(0) exp(-(1 + eps) t / t_s) for dv = v_g - v_d
+    and keeps the centre-of-mass velocity; the IMEX2P steps converge to it at second
+    order, and stay stable and decaying at dt far above t_s."""
+    eps, ts, v0 = 0.3, 0.1, (0.7, -0.2)
+    fl = [(np.full((1, 1, 1), 1.0), np.full((1, 1, 1), v0[0]), np.zeros((1, 1, 1)), np.zeros((1, 1, 1))),
+          (np.full((1, 1, 1), eps), np.full((1, 1, 1), v0[1]), np.zeros((1, 1, 1)), np.zeros((1, 1, 1)))]
+    st = I.dust_state(fl)
+    c = oracle.make_cfg((1, 1, 1), eos="isothermal_hydro", tstop=[ts], recon="plm", integ="imex2p")
+    T = 0.5
+    exact = (v0[0] - v0[1]) * math.exp(-(1.0 + eps) * T / ts)
+    vcm = (v0[0] + eps * v0[1]) / (1.0 + eps)
+    errs = []
+    for nst in (100, 200, 400):
+        s = st.copy()
+        for _ in range(nst):
+            s = oracle.step(c, s, T / nst)
+        vg, vd = s[1] / s[0], s[5] / s[4]
+        assert abs((vg + eps * vd) / (1.0 + eps) - vcm) < 1e-13  # round-off over the steps
+        errs.append(abs((vg - vd) - exact))
+    assert errs[0] < 1e-3 * abs(v0[0] - v0[1])
+    assert math.log2(errs[0] / errs[1]) > 1.85 and math.log2(errs[1] / errs[2]) > 1.9, errs
+    # stiff: dt = 100 t_s, the relative velocity decays monotonically towards zero
+    s = st.copy()
+    prev = abs(v0[0] - v0[1])
+    for _ in range(5):
+        s = oracle.step(c, s, 100.0 * ts)
+        dv = abs(s[1] / s[0] - s[5] / s[4])
+        assert dv < prev
+        prev = dv
+    assert prev < 1e-3 * abs(v0[0] - v0[1])
+
+
 def test_stiff_drag_reaches_the_drift_equilibrium():
     g, st, c = _relax_setup()
     ts = np.array(g["ts"])

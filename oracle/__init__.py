@@ -82,6 +82,8 @@ def _lib():
         L.orc_drag_solve.restype = None
         L.orc_rhs_mhd_debug.argtypes = [cp, ctypes.c_int, dp, dp, dp, dp]
         L.orc_rhs_mhd_debug.restype = None
+        L.orc_mhd_prims.argtypes = [cp, dp, dp]
+        L.orc_mhd_prims.restype = None
         _lib_handle = L
     return _lib_handle
 
@@ -192,6 +194,15 @@ def drag_solve(rho, p, ts, h: float) -> np.ndarray:
     out = np.zeros_like(p)
     _lib().orc_drag_solve(len(ts), _ptr(rho), _ptr(p), _ptr(ts), float(h), _ptr(out))
     return out
+
+
+def mhd_prims(cfg: OrcCfg, state: np.ndarray) -> np.ndarray:
+    """The 8 cell primitives of an MHD state as a stage computes them, [8][nz][ny][nx]."""
+    s = np.ascontiguousarray(state, dtype=np.float64)
+    nc = cfg.nx * cfg.ny * cfg.nz
+    out = np.zeros(8 * nc)
+    _lib().orc_mhd_prims(ctypes.byref(cfg), _ptr(s), _ptr(out))
+    return out.reshape(8, cfg.nz, cfg.ny, cfg.nx)
 
 
 def rhs_mhd_debug(cfg: OrcCfg, recon: str, state: np.ndarray):

@@ -634,6 +634,26 @@ void orc_rhs_mhd_debug(const orc_cfg* c, int recon, const double* state, double*
     mhd_work_free(&W);
 }
 
+/* The 8 cell primitives (rho, v, p, B_cc) of an MHD state as the stage computes them,
+ * interior cells, [8][nz][ny][nx]; for tests. */
+void orc_mhd_prims(const orc_cfg* c, const double* state, double* prims)
+{
+    mhd_work W;
+    mhd_work_alloc(&W, c);
+    const grid_t* g = &W.g;
+    long nc = ncell(g);
+    for (int q = 0; q < 5; ++q) pad_field(g, state + q * nc, W.u[q]);
+    for (int q = 0; q < 3; ++q) pad_field(g, state + (5 + q) * nc, W.b[q]);
+    mhd_prims(c, &W);
+    for (int k = 0; k < g->n[2]; ++k)
+        for (int j = 0; j < g->n[1]; ++j)
+            for (int i = 0; i < g->n[0]; ++i) {
+                long id = at(g, i, j, k), ci = cell(g, i, j, k);
+                for (int q = 0; q < 8; ++q) prims[q * nc + ci] = W.w[q][id];
+            }
+    mhd_work_free(&W);
+}
+
 /* ------------------------------------------------------------------------------ */
 /* isothermal gas + N pressureless dust: explicit part F(u) and drag G(u)           */
 /* ------------------------------------------------------------------------------ */

@@ -92,6 +92,10 @@ void orc_drag_solve(int n, const double* rho, const double* p, const double* ts,
 void orc_rhs_mhd_debug(const orc_cfg* cfg, int recon, const double* state, double* dudt,
                        double* emf, double* facee);
 
+/* Cell primitives (rho, vx, vy, vz, p, Bx, By, Bz; floors applied, B_cc the mean of
+ * the two bounding faces) of an MHD state, interior cells, [8][nz][ny][nx]. */
+void orc_mhd_prims(const orc_cfg* cfg, const double* state, double* prims);
+
 #ifdef __cplusplus
 }
 #endif

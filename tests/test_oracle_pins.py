@@ -34,6 +34,47 @@ def read_golden(name):
 # reconstruction
 # ----------------------------------------------------------------------------------
 
+def test_primitive_recovery_round_trip():
+    """Random primitives -> conserved state by the definitions (E = p/(gamma-1) +
+    rho v^2/2 + B^2/2 with B_cc the mean of the two bounding faces, faces from a
+    potential) -> the oracle's primitive recovery returns them to a few ulp; floors
+    replace a density or pressure below them and nothing else."""
+    rng = np.random.default_rng(11)
+    shape = (7, 5, 4)
+    nx, ny, nz = shape
+    gamma = 5.0 / 3.0
+    full = (nz, ny, nx)
+    rho = rng.uniform(0.2, 3.0, full)
+    v = [rng.normal(0, 1.0, full) for _ in range(3)]
+    p = rng.uniform(0.05, 2.0, full)
+    dx = [1.0 / shape[a] for a in range(3)]
+    pots = [rng.normal(0, 0.2 / max(shape), full) for _ in range(3)]
+    b1, b2, b3 = I.faces_from_potential(*pots, *dx)
+    b1, b2, b3 = b1 + 0.4, b2 - 0.7, b3 + 0.1
+    bx = 0.5 * (b1 + np.roll(b1, -1, axis=2))
+    by = 0.5 * (b2 + np.roll(b2, -1, axis=1))
+    bz = 0.5 * (b3 + np.roll(b3, -1, axis=0))
+    E = p / (gamma - 1.0) + 0.5 * rho * (v[0] ** 2 + v[1] ** 2 + v[2] ** 2) + 0.5 * (bx ** 2 + by ** 2 + bz ** 2)
+    st = np.concatenate([a.reshape(-1) for a in (rho, rho * v[0], rho * v[1], rho * v[2], E, b1, b2, b3)])
+    c = oracle.make_cfg(shape, gamma=gamma)
+    w = oracle.mhd_prims(c, st)
+    want = [rho, v[0], v[1], v[2], p, bx, by, bz]
+    for q in range(8):
+        assert np.allclose(w[q], want[q], rtol=2e-15 if q != 4 else 1e-13, atol=0.0), q
+    # the pressure is recovered from E: its error is that of E (a few ulp of E) over (gamma-1)
+    assert np.abs(w[4] - p).max() <= 8 * np.finfo(float).eps * np.abs(E).max()
+    # floors: a cell with too little density and one with negative pressure
+    st2 = st.copy()
+    n = nx * ny * nz
+    st2[0] = 1e-20
+    st2[4 * n + 1] = -1.0
+    c2 = oracle.make_cfg(shape, gamma=gamma, rho_floor=1e-8, p_floor=1e-6)
+    w2 = oracle.mhd_prims(c2, st2)
+    assert w2[0].reshape(-1)[0] == 1e-8
+    assert w2[4].reshape(-1)[1] == 1e-6
+    assert np.array_equal(w2[0].reshape(-1)[1:], rho.reshape(-1)[1:])
+
+
 @pytest.mark.parametrize("recon", ["plm", "ppm"])
 def test_recon_exact_on_linear_data(recon):
     n = 40

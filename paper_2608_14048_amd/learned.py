@@ -257,9 +257,9 @@ def main():
     ap.add_argument("--out", required=True)
     ap.add_argument("--nc", type=int, default=64)
     ap.add_argument("--r", type=int, default=4)
-    ap.add_argument("--train-seeds", type=int, default=24)
-    ap.add_argument("--eval-seeds", type=int, default=4)
-    ap.add_argument("--iters", type=int, default=1500)
+    ap.add_argument("--train-seeds", type=int, default=128)
+    ap.add_argument("--eval-seeds", type=int, default=16)
+    ap.add_argument("--iters", type=int, default=12000)
     args = ap.parse_args()
     train_seeds = list(range(100, 100 + args.train_seeds))
     eval_seeds = list(range(900, 900 + args.eval_seeds))

@@ -5,6 +5,10 @@
 //                      z planes; writes the 21 face fields and the 3 cell-E fields.
 // k_ct_update<CFL, IN> same tiling with 8 rows (one halo row per 8); edge EMFs, the
 //                      cell and face updates and, in the last stage, the CFL partials.
+//                      The FP64 kernel that also reduces the time step uses 4 rows: it
+//                      then keeps the previous plane's values in registers at three
+//                      workgroups per CU (with 8 rows they would cost it half its
+//                      occupancy).
 #include "mhd_tiles.hpp"
 
 namespace mhd {
@@ -31,17 +35,17 @@ __global__ __launch_bounds__(TX* TY) void k_flux3(Geo g, MhdParams P, RegView<R>
     Tile::run(g, P, U, F, Rc, x0, y0, k0, min(k0 + kz, g.nz), lds);
 }
 
-template <bool CFL, bool IN, class R>
-__global__ __launch_bounds__(TX* TY2) void k_ct_update(Geo g, MhdParams P, CtArgs<R> a, int kz,
+template <bool CFL, bool IN, class R, int TYC>
+__global__ __launch_bounds__(TX* TYC) void k_ct_update(Geo g, MhdParams P, CtArgs<R> a, int kz,
                                                       unsigned int ntx, unsigned int nty,
                                                       unsigned int nblk)
 {
-    using Tile = CtTile<CFL, IN, R, TX, TY2>;
+    using Tile = CtTile<CFL, IN, R, TX, TYC>;
     __shared__ typename Tile::Lds lds;
-    __shared__ double sMin[TX * TY2 / 64];
+    __shared__ double sMin[TX * TYC / 64];
     const unsigned int bt = xcd_tile(blockIdx.x, nblk);
     const int x0 = (int)(bt % ntx) * TX;
-    const int y0 = (int)((bt / ntx) % nty) * TY2;
+    const int y0 = (int)((bt / ntx) % nty) * TYC;
     const int k0 = (int)(bt / (ntx * nty)) * kz;
     double vmin = Tile::run(g, P, a, x0, y0, k0, min(k0 + kz, g.nz), lds);
     if (CFL) {
@@ -51,7 +55,7 @@ __global__ __launch_bounds__(TX* TY2) void k_ct_update(Geo g, MhdParams P, CtArg
         if (threadIdx.x == 0) {
             double r = sMin[0];
 #pragma unroll
-            for (int w = 1; w < TX * TY2 / 64; ++w) r = min_nan(r, sMin[w]);
+            for (int w = 1; w < TX * TYC / 64; ++w) r = min_nan(r, sMin[w]);
             a.partial[blockIdx.x] = r;
         }
     }
@@ -148,18 +152,23 @@ static hipError_t ct_update(const Geo& g, const MhdParams& p, const FusedGrid& f
     const bool use_in = coef.g0 != 0.0 || p.gacc[0] != 0.0 || p.gacc[1] != 0.0 || p.gacc[2] != 0.0;
     const dim3 gr(fg.nblk2), bl(TX * TY2);
     if (dt_out) {
+        // FP64: 4-row tiles (the flux kernel's tiling); FP32: 8 rows
+        constexpr int TYC = sizeof(R) == 8 ? TY : TY2;
+        const unsigned int nty = sizeof(R) == 8 ? fg.nty : fg.nty2;
+        const unsigned int nblk = sizeof(R) == 8 ? fg.nblk : fg.nblk2;
+        const dim3 grc(nblk), blc(TX * TYC);
         if (use_in)
-            hipLaunchKernelGGL((k_ct_update<true, true, R>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty2, fg.nblk2);
+            hipLaunchKernelGGL((k_ct_update<true, true, R, TYC>), grc, blc, 0, s, g, p, a, fg.kz, fg.ntx, nty, nblk);
         else
-            hipLaunchKernelGGL((k_ct_update<true, false, R>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty2, fg.nblk2);
+            hipLaunchKernelGGL((k_ct_update<true, false, R, TYC>), grc, blc, 0, s, g, p, a, fg.kz, fg.ntx, nty, nblk);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        return launch_min_final(partial, fg.nblk2, cfl_scale, dt_out, s);
+        return launch_min_final(partial, nblk, cfl_scale, dt_out, s);
     }
     if (use_in)
-        hipLaunchKernelGGL((k_ct_update<false, true, R>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty2, fg.nblk2);
+        hipLaunchKernelGGL((k_ct_update<false, true, R, TY2>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty2, fg.nblk2);
     else
-        hipLaunchKernelGGL((k_ct_update<false, false, R>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty2, fg.nblk2);
+        hipLaunchKernelGGL((k_ct_update<false, false, R, TY2>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty2, fg.nblk2);
     return hipGetLastError();
 }
 

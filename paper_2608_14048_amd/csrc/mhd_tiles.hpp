@@ -407,10 +407,11 @@ struct CtTile {
         // stay in registers (cx*, cy*) instead of coming back from memory, for the
         // first NC edge positions of the thread.  Likewise the z fluxes of the high face
         // (fzc) and, with CFL, the updated B_z of the high face (b3c) carry over to the
-        // plane above.  The FP64 kernel that also reduces the time step carries nothing:
-        // the extra registers would cost it half its occupancy, which it needs more.
+        // plane above.  An FP64 kernel that also reduces the time step on tiles taller
+        // than 4 rows carries nothing: at 512 threads the extra registers would cost it
+        // half its occupancy, which it needs more.
         constexpr int NT = TX * TY, NE = (TX + 1) * (TY + 1), NQ = (NE + NT - 1) / NT;
-        constexpr bool ZC = !(CFL && sizeof(R) == 8);
+        constexpr bool ZC = !(CFL && sizeof(R) == 8 && TY > 4);
         constexpr int NC = !ZC ? 0 : (sizeof(R) == 4 ? NQ : 1);
         constexpr int NA = NC > 0 ? NC : 1;
         R cx13[NA], cx7[NA], crx0[NA], crxm[NA], cy5[NA], cy0[NA], cry0[NA], cryx[NA];

@@ -126,3 +126,33 @@ def test_batch_validation_before_touching_the_device():
     with pytest.raises(B.MhdError) as e:
         B.mhd_batch_create(grids, phys, scheme, fake + 8, nb, 0)
     assert e.value.code == -1
+
+
+def test_closure_validation_before_touching_the_device():
+    from oracle import closure as OC
+    # the parameter layout the library takes is the reference's
+    assert B.mhd_cnn_param_count() == OC.param_count() == 77874
+    phys = B.make_physics()
+    nb = B.mhd_cnn_workspace_bytes(B.make_grid((64, 64, 64)), phys)
+    # parameters, gradients and two Adam moments in FP32 at least
+    assert nb >= 4 * 4 * 77874
+    assert B.mhd_cnn_workspace_bytes(B.make_grid((64, 32, 16)), phys) < nb
+    cases = [
+        (B.make_grid((24, 16, 16)), phys, -2),                         # x not a multiple of 16
+        (B.make_grid((8, 16, 16)), phys, -1),                          # narrower than one MFMA block
+        (B.make_grid((512, 512, 256)), phys, -2),                      # 2^26 cells
+        (B.make_grid((64, 64, 64)), B.make_physics(eos="isothermal_hydro", tstop=(1.0,)), -2),
+        (B.make_grid((64, 64, 64)), B.make_physics(gamma=1.0), -2),
+    ]
+    for grid, ph, code in cases:
+        with pytest.raises(B.MhdError) as e:
+            B.mhd_cnn_workspace_bytes(grid, ph)
+        assert e.value.code == code
+    fake = 1 << 40  # never dereferenced: create rejects before any device call
+    g64 = B.make_grid((64, 64, 64))
+    with pytest.raises(B.MhdError) as e:
+        B.mhd_cnn_create(g64, phys, fake, nb - 256, 0)
+    assert e.value.code == -3
+    with pytest.raises(B.MhdError) as e:
+        B.mhd_cnn_create(g64, phys, fake + 8, nb, 0)
+    assert e.value.code == -1

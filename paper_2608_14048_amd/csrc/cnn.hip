@@ -185,6 +185,94 @@ __global__ __launch_bounds__(kThreads) void k_conv(Geo g, const bf16_t* __restri
     }
 }
 
+// The same convolution with its input staged in LDS: one workgroup computes a
+// 16 x 4 x 4 block of voxels (wave w the 4 rows of plane z0 + w), and the block's
+// input with a one-voxel halo, 18 x 6 x 6 voxels of CINP channels, is read from memory
+// once into LDS instead of once per tap; every tap's A fragments then come from LDS.
+// The accumulation order (taps, then K chunks) is that of k_conv, so the results are
+// bitwise the same.  Needs ny and nz to be multiples of 4 (nx is one of 16).
+constexpr int kTileY = 4, kTileZ = 4;
+constexpr int kHalo = 18 * (kTileY + 2) * (kTileZ + 2);  // staged voxels
+
+template <int CINP, int MODE>
+__global__ __launch_bounds__(kThreads) void k_conv_lds(Geo g, const bf16_t* __restrict__ X,
+                                                       const bf16_t* __restrict__ B,
+                                                       const float* __restrict__ bias,
+                                                       const bf16_t* __restrict__ M, bf16_t* __restrict__ Y,
+                                                       float* __restrict__ O, int nstore)
+{
+    constexpr int CSTR = CINP + 4;  // channels per staged voxel, padded (8-byte aligned rows)
+    __shared__ __align__(16) bf16_t sA[kTileZ + 2][kTileY + 2][18][CSTR];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const unsigned int ntx = (unsigned int)g.nx / 16u, nty = (unsigned int)g.ny / kTileY;
+    const unsigned int b = blockIdx.x;
+    const int x0 = (int)(b % ntx) * 16;
+    const int y0 = (int)((b / ntx) % nty) * kTileY;
+    const int z0 = (int)(b / (ntx * nty)) * kTileZ;
+    const unsigned int n = (unsigned int)g.n;
+
+    // stage the input block with its halo (periodic), 8 bytes per load
+    constexpr int CH = CINP / 4;
+    for (int q = threadIdx.x; q < kHalo * CH; q += kThreads) {
+        const int vq = q / CH, part = q - vq * CH;
+        const int lx = vq % 18, ly = (vq / 18) % (kTileY + 2), lz = vq / (18 * (kTileY + 2));
+        const unsigned int gv = ((unsigned int)wrap1(z0 + lz - 1, g.nz) * (unsigned int)g.ny +
+                                 (unsigned int)wrap1(y0 + ly - 1, g.ny)) * (unsigned int)g.nx +
+                                (unsigned int)wrap1(x0 + lx - 1, g.nx);
+        *reinterpret_cast<uint2*>(&sA[lz][ly][lx][part * 4]) =
+            *reinterpret_cast<const uint2*>(X + (size_t)gv * CINP + part * 4);
+    }
+    __syncthreads();
+
+    const int lr = lane & 15, lk = (lane >> 4) * 4;
+    f4 acc[4][2];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 27; ++t) {
+        const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+#pragma unroll
+        for (int kc = 0; kc < CINP / 16; ++kc) {
+            s4 bf[2];
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+                bf[cb] = *reinterpret_cast<const s4*>(B + ((size_t)(t * kNPad + cb * 16 + lr) * CINP + kc * 16 + lk));
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                const s4 af = *reinterpret_cast<const s4*>(&sA[w + dz + 1][rb + dy + 1][lr + dx + 1][kc * 16 + lk]);
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bf[cb], acc[rb][cb], 0, 0, 0);
+            }
+        }
+    }
+    // accumulator element i of lane l: row (voxel) 4*(l/16) + i, column (channel) l % 16
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+        const unsigned int vrow = ((unsigned int)(z0 + w) * (unsigned int)g.ny + (unsigned int)(y0 + rb)) *
+                                  (unsigned int)g.nx + (unsigned int)x0;
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            const int nn = cb * 16 + lr;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const unsigned int v = vrow + lk + i;
+                float val = acc[rb][cb][i];
+                if (MODE == 0) {
+                    val = fmaxf(val + bias[nn], 0.f);
+                    Y[(size_t)v * kNPad + nn] = f2bf(val);
+                } else if (MODE == 1) {
+                    if (nn < nstore) O[(size_t)nn * n + v] = val + bias[nn];
+                } else {
+                    if (!(bf2f(M[(size_t)v * kNPad + nn]) > 0.f)) val = 0.f;
+                    Y[(size_t)v * kNPad + nn] = f2bf(val);
+                }
+            }
+        }
+    }
+}
+
 // dW[t][k][nn] += sum_v X[v + off(t)][k] D[v][nn] over a chunk of voxels per wavefront,
 // added into the canonical FP32 gradient of the layer (k < cin, nn < cout only).
 template <int CINP>
@@ -491,20 +579,31 @@ hipError_t pack_all(mhd_cnn* c)
     return hipGetLastError();
 }
 
+// One convolution launch: the LDS-staged kernel where the grid tiles into 16 x 4 x 4
+// blocks, else the per-tap gather kernel (both give the same bits).
+template <int CINP, int MODE>
+void conv(const mhd_cnn* c, const bf16_t* X, const bf16_t* B, const float* bias, const bf16_t* M, bf16_t* Y,
+          float* O, int nstore)
+{
+    if (c->g.ny % kTileY == 0 && c->g.nz % kTileZ == 0) {
+        const unsigned int nblk = (unsigned int)(c->g.n / (16 * kTileY * kTileZ));
+        hipLaunchKernelGGL((k_conv_lds<CINP, MODE>), dim3(nblk), dim3(kThreads), 0, c->stream, c->g, X, B, bias, M,
+                           Y, O, nstore);
+    } else {
+        hipLaunchKernelGGL((k_conv<CINP, MODE>), dim3(conv_blocks(c)), dim3(kThreads), 0, c->stream, c->g, X, B,
+                           bias, M, Y, O, nstore);
+    }
+}
+
 // forward pass from a canonical state; keeps every layer input for the backward pass
 hipError_t forward(mhd_cnn* c, const double* U)
 {
     hipLaunchKernelGGL(k_cnn_input, dim3(c->nblk), dim3(kThreads), 0, c->stream, c->g, c->gamma, U, c->scal,
                        c->scal + 8, c->A[0]);
-    const dim3 gr(conv_blocks(c)), bl(kThreads);
-    hipLaunchKernelGGL((k_conv<16, 0>), gr, bl, 0, c->stream, c->g, c->A[0], c->Wf[0], c->P + param_offset(0) + layer_w(0),
-                       nullptr, c->A[1], nullptr, 0);
-    hipLaunchKernelGGL((k_conv<32, 0>), gr, bl, 0, c->stream, c->g, c->A[1], c->Wf[1], c->P + param_offset(1) + layer_w(1),
-                       nullptr, c->A[2], nullptr, 0);
-    hipLaunchKernelGGL((k_conv<32, 0>), gr, bl, 0, c->stream, c->g, c->A[2], c->Wf[2], c->P + param_offset(2) + layer_w(2),
-                       nullptr, c->A[3], nullptr, 0);
-    hipLaunchKernelGGL((k_conv<32, 1>), gr, bl, 0, c->stream, c->g, c->A[3], c->Wf[3], c->P + param_offset(3) + layer_w(3),
-                       nullptr, nullptr, c->O, 18);
+    conv<16, 0>(c, c->A[0], c->Wf[0], c->P + param_offset(0) + layer_w(0), nullptr, c->A[1], nullptr, 0);
+    conv<32, 0>(c, c->A[1], c->Wf[1], c->P + param_offset(1) + layer_w(1), nullptr, c->A[2], nullptr, 0);
+    conv<32, 0>(c, c->A[2], c->Wf[2], c->P + param_offset(2) + layer_w(2), nullptr, c->A[3], nullptr, 0);
+    conv<32, 1>(c, c->A[3], c->Wf[3], c->P + param_offset(3) + layer_w(3), nullptr, nullptr, c->O, 18);
     return hipGetLastError();
 }
 
@@ -681,7 +780,7 @@ mhd_status mhd_cnn_accumulate(mhd_cnn* c, const double* state_t, const double* c
     hipLaunchKernelGGL(k_out_grad, dim3(c->nblk), dim3(kThreads), 0, c->stream, c->g, c->RW, c->scal + 16, c->sE, dt,
                        c->D0);
     // backward: layer l consumes D (its output gradient) and A[l] (its input)
-    const dim3 gr(conv_blocks(c)), bl(kThreads);
+    const dim3 bl(kThreads);
     const unsigned int vchunk = 1024;
     const unsigned int wwaves = 27u * (unsigned int)((c->g.n + vchunk - 1) / vchunk);
     const dim3 gw((wwaves + 3) / 4);
@@ -698,7 +797,7 @@ mhd_status mhd_cnn_accumulate(mhd_cnn* c, const double* state_t, const double* c
         hipLaunchKernelGGL(k_bgrad, dim3(bblk), bl, 0, c->stream, c->g, D, Gb, kCout[l]);
         if (l > 0) {
             // gradient of layer l's input, through the ReLU of layer l-1 (mask = A[l] > 0)
-            hipLaunchKernelGGL((k_conv<32, 2>), gr, bl, 0, c->stream, c->g, D, c->Wb[l], nullptr, c->A[l], Dn, nullptr, 0);
+            conv<32, 2>(c, D, c->Wb[l], nullptr, c->A[l], Dn, nullptr, 0);
             bf16_t* t = D;
             D = Dn;
             Dn = t;

@@ -90,8 +90,10 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
 
-def test_forward_matches_bf16_reference():
-    shape = (16, 8, 12)
+# (16, 8, 12) tiles into the LDS-staged 16 x 4 x 4 convolution blocks; (32, 6, 5) does
+# not and takes the per-tap gather kernel
+@pytest.mark.parametrize("shape", [(16, 8, 12), (32, 6, 5)])
+def test_forward_matches_bf16_reference(shape):
     st, L, cl, params, mu, sd, sF, sE, wU, wB, _ = setup(shape, 1)
     try:
         out = cl.forward(dev(st)).cpu().numpy().reshape(18, shape[2], shape[1], shape[0])

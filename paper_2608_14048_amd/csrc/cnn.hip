@@ -186,15 +186,16 @@ __global__ __launch_bounds__(kThreads) void k_conv(Geo g, const bf16_t* __restri
 }
 
 // The same convolution with its input staged in LDS: one workgroup computes a
-// 16 x 4 x 4 block of voxels (wave w the 4 rows of plane z0 + w), and the block's
-// input with a one-voxel halo, 18 x 6 x 6 voxels of CINP channels, is read from memory
-// once into LDS instead of once per tap; every tap's A fragments then come from LDS.
-// The accumulation order (taps, then K chunks) is that of k_conv, so the results are
-// bitwise the same.  Needs ny and nz to be multiples of 4 (nx is one of 16).
-constexpr int kTileY = 4, kTileZ = 4;
-constexpr int kHalo = 18 * (kTileY + 2) * (kTileZ + 2);  // staged voxels
+// 16 x 4 x 4TZ block of voxels (wave w the 4 rows of planes z0 + TZ w ..), and the
+// block's input with a one-voxel halo, 18 x 6 x (4TZ + 2) voxels of CINP channels, is
+// read from memory once into LDS instead of once per tap; every tap's A fragments then
+// come from LDS.  The accumulation order (taps, then K chunks) is that of k_conv, so
+// the results are bitwise the same.  Needs ny a multiple of 4 and nz one of 4TZ (nx is
+// one of 16).
+constexpr int kTileY = 4;
 
-template <int CINP, int MODE>
+// TZ: planes per wavefront (the block is 16 x 4 x 4 TZ voxels)
+template <int CINP, int MODE, int TZ>
 __global__ __launch_bounds__(kThreads) void k_conv_lds(Geo g, const bf16_t* __restrict__ X,
                                                        const bf16_t* __restrict__ B,
                                                        const float* __restrict__ bias,
@@ -202,6 +203,8 @@ __global__ __launch_bounds__(kThreads) void k_conv_lds(Geo g, const bf16_t* __re
                                                        float* __restrict__ O, int nstore)
 {
     constexpr int CSTR = CINP + 4;  // channels per staged voxel, padded (8-byte aligned rows)
+    constexpr int kTileZ = 4 * TZ, kHalo = 18 * (kTileY + 2) * (kTileZ + 2);
+    constexpr int NRB = 4 * TZ;     // 16-voxel row blocks per wavefront
     __shared__ __align__(16) bf16_t sA[kTileZ + 2][kTileY + 2][18][CSTR];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const unsigned int ntx = (unsigned int)g.nx / 16u, nty = (unsigned int)g.ny / kTileY;
@@ -225,9 +228,10 @@ __global__ __launch_bounds__(kThreads) void k_conv_lds(Geo g, const bf16_t* __re
     __syncthreads();
 
     const int lr = lane & 15, lk = (lane >> 4) * 4;
-    f4 acc[4][2];
+    // row block rb of wave w: row y0 + rb % 4 of plane z0 + TZ w + rb / 4
+    f4 acc[NRB][2];
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+    for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
     for (int t = 0; t < 27; ++t) {
@@ -239,8 +243,9 @@ __global__ __launch_bounds__(kThreads) void k_conv_lds(Geo g, const bf16_t* __re
             for (int cb = 0; cb < 2; ++cb)
                 bf[cb] = *reinterpret_cast<const s4*>(B + ((size_t)(t * kNPad + cb * 16 + lr) * CINP + kc * 16 + lk));
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) {
-                const s4 af = *reinterpret_cast<const s4*>(&sA[w + dz + 1][rb + dy + 1][lr + dx + 1][kc * 16 + lk]);
+            for (int rb = 0; rb < NRB; ++rb) {
+                const s4 af = *reinterpret_cast<const s4*>(
+                    &sA[TZ * w + rb / 4 + dz + 1][rb % 4 + dy + 1][lr + dx + 1][kc * 16 + lk]);
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb)
                     acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bf[cb], acc[rb][cb], 0, 0, 0);
@@ -249,9 +254,9 @@ __global__ __launch_bounds__(kThreads) void k_conv_lds(Geo g, const bf16_t* __re
     }
     // accumulator element i of lane l: row (voxel) 4*(l/16) + i, column (channel) l % 16
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-        const unsigned int vrow = ((unsigned int)(z0 + w) * (unsigned int)g.ny + (unsigned int)(y0 + rb)) *
-                                  (unsigned int)g.nx + (unsigned int)x0;
+    for (int rb = 0; rb < NRB; ++rb) {
+        const unsigned int vrow = ((unsigned int)(z0 + TZ * w + rb / 4) * (unsigned int)g.ny +
+                                   (unsigned int)(y0 + rb % 4)) * (unsigned int)g.nx + (unsigned int)x0;
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
             const int nn = cb * 16 + lr;
@@ -579,16 +584,21 @@ hipError_t pack_all(mhd_cnn* c)
     return hipGetLastError();
 }
 
-// One convolution launch: the LDS-staged kernel where the grid tiles into 16 x 4 x 4
-// blocks, else the per-tap gather kernel (both give the same bits).
+// One convolution launch: the LDS-staged kernel where the grid tiles into 16 x 4 x 8 or
+// 16 x 4 x 4 blocks, else the per-tap gather kernel (all give the same bits).
 template <int CINP, int MODE>
 void conv(const mhd_cnn* c, const bf16_t* X, const bf16_t* B, const float* bias, const bf16_t* M, bf16_t* Y,
           float* O, int nstore)
 {
-    if (c->g.ny % kTileY == 0 && c->g.nz % kTileZ == 0) {
-        const unsigned int nblk = (unsigned int)(c->g.n / (16 * kTileY * kTileZ));
-        hipLaunchKernelGGL((k_conv_lds<CINP, MODE>), dim3(nblk), dim3(kThreads), 0, c->stream, c->g, X, B, bias, M,
-                           Y, O, nstore);
+    if (c->g.ny % kTileY == 0 && c->g.nz % 8 == 0) {
+        // 16 x 4 x 8 blocks, two planes per wavefront (78 KB of LDS: two workgroups per CU)
+        const unsigned int nblk = (unsigned int)(c->g.n / (16 * kTileY * 8));
+        hipLaunchKernelGGL((k_conv_lds<CINP, MODE, 2>), dim3(nblk), dim3(kThreads), 0, c->stream, c->g, X, B, bias,
+                           M, Y, O, nstore);
+    } else if (c->g.ny % kTileY == 0 && c->g.nz % 4 == 0) {
+        const unsigned int nblk = (unsigned int)(c->g.n / (16 * kTileY * 4));
+        hipLaunchKernelGGL((k_conv_lds<CINP, MODE, 1>), dim3(nblk), dim3(kThreads), 0, c->stream, c->g, X, B, bias,
+                           M, Y, O, nstore);
     } else {
         hipLaunchKernelGGL((k_conv<CINP, MODE>), dim3(conv_blocks(c)), dim3(kThreads), 0, c->stream, c->g, X, B,
                            bias, M, Y, O, nstore);

@@ -335,7 +335,8 @@ def batch_leg(nblocks: int, steps: int, warmup: int, prec: str = "fp32_bulk", se
             "separate_launches_value": mz(el_sep),
             "separate_launches_ms_per_step": round(el_sep * 1e3 / steps, 4),
             "speedup_vs_separate": round(el_sep / el_tuned, 2),
-            "tuned_shape_per_x_extent": {str(x): int(np.argmin(tune_ms[q])) for q, x in enumerate(classes)},
+            "tuned_shape_per_x_extent": {str(x): int(chosen[[sh[0] for sh in shapes].index(x)]) for x in classes},
+            "fastest_alone_per_x_extent": {str(x): int(np.argmin(tune_ms[q])) for q, x in enumerate(classes)},
             "tune_ms_per_pass": {str(x): [round(float(v), 4) for v in tune_ms[q]] for q, x in enumerate(classes)}}
 
 

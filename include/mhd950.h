@@ -237,9 +237,10 @@ mhd_status mhd_batch_get_shapes(const mhd_batch* batch, int* shapes, int nblocks
 
 /* Autotuner: for each class of blocks with one x extent (classes in increasing nx),
  * time `reps` passes of the configured-reconstruction stage over that class alone with
- * each tile shape, keep the fastest, and rebuild the work queue.  The current state is
- * only read.  If ms_out is not NULL it receives the average ms per pass, class-major
- * (nout >= classes * 3).  Synchronises the stream. */
+ * each tile shape; then time the whole batch with those per-class picks and with each
+ * uniform shape, keep the fastest assignment, and rebuild the work queue.  The current
+ * state is only read.  If ms_out is not NULL it receives the per-class average ms per
+ * pass, class-major (nout >= classes * 3).  Synchronises the stream. */
 mhd_status mhd_batch_tune(mhd_batch* batch, int reps, float* ms_out, int nout);
 
 void mhd_batch_destroy(mhd_batch* batch);

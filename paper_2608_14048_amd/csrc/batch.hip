@@ -720,6 +720,36 @@ mhd_status mhd_batch_tune(mhd_batch* c, int reps, float* ms_out, int nout)
             }
         }
     }
+    // Classes share launches and the GPU, so the per-class optimum need not be the best
+    // whole: time the full batch with it and with each uniform shape, keep the fastest.
+    auto class_of = [&](int b) { return (int)(std::lower_bound(xs.begin(), xs.end(), c->geo[b].nx) - xs.begin()); };
+    std::vector<std::vector<int>> cands;
+    {
+        std::vector<int> a(c->nb);
+        for (int b = 0; b < c->nb; ++b) a[b] = best[class_of(b)];
+        cands.push_back(a);
+        for (int s = 0; s < kShapes; ++s) cands.push_back(std::vector<int>(c->nb, s));
+    }
+    int pick = 0;
+    float tpick = 0.0f;
+    for (size_t k = 0; k < cands.size() && st == MHD_OK; ++k) {
+        c->shape = cands[k];
+        st = build_all(c);
+        if (st != MHD_OK) break;
+        float ms = 0.0f;
+        for (int r = 0; r <= reps && st == MHD_OK; ++r) {
+            if (r == 1 && hipEventRecord(e0, c->stream) != hipSuccess) st = MHD_E_DEVICE;
+            if (st == MHD_OK)
+                st = bstage(c, c->scheme.recon, c->reg[s0], c->reg[s0], c->reg[s1], 0.0, 1.0, 1.0, false);
+        }
+        if (st == MHD_OK && hipEventRecord(e1, c->stream) != hipSuccess) st = MHD_E_DEVICE;
+        if (st == MHD_OK && hipEventSynchronize(e1) != hipSuccess) st = MHD_E_DEVICE;
+        if (st == MHD_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = MHD_E_DEVICE;
+        if (st == MHD_OK && (k == 0 || ms < tpick)) {
+            tpick = ms;
+            pick = (int)k;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != MHD_OK) {
@@ -727,8 +757,7 @@ mhd_status mhd_batch_tune(mhd_batch* c, int reps, float* ms_out, int nout)
         (void)build_all(c);
         return st;
     }
-    for (int b = 0; b < c->nb; ++b)
-        c->shape[b] = best[std::lower_bound(xs.begin(), xs.end(), c->geo[b].nx) - xs.begin()];
+    c->shape = cands[pick];
     return build_all(c);
 }
 

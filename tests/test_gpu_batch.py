@@ -89,10 +89,12 @@ def test_tile_shapes_and_tuning_do_not_change_results():
                 ms = bt.tune(reps=2)
                 _say(f"  tuned ms per pass [class x shape]:\n{ms}")
                 assert np.all(np.isfinite(ms)) and np.all(ms > 0)
-                chosen = bt.tile_shapes()
-                for b, sh in enumerate(shapes):
-                    q = bt.classes.index(sh[0])
-                    assert chosen[b] == int(np.argmin(ms[q])), (b, chosen[b], ms[q])
+                chosen = list(bt.tile_shapes())
+                # the tuner keeps the per-class picks or a uniform shape, whichever ran
+                # the whole batch fastest
+                per_class = [int(np.argmin(ms[bt.classes.index(sh[0])])) for sh in shapes]
+                cands = [per_class] + [[s] * len(shapes) for s in range(3)]
+                assert chosen in cands, (chosen, per_class)
                 bt.set_state(states)  # tuning only reads the state; start over anyway
             else:
                 bt.set_tile_shapes(shp)

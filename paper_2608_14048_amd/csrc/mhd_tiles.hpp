@@ -140,8 +140,10 @@ __device__ __forceinline__ void solve(const Prim7<R>& L, const Prim7<R>& Rt, R b
 }
 
 // Reconstruction along z as a pipeline over the planes a column visits: each new plane
-// costs one slope, one interface and one limiter (PPM), one slope (PLM) or nothing (DC);
-// push() returns the two states on the face k - 1/2 when plane k + AHEAD arrives.
+// costs one slope, one interface and one limiter (PPM), one slope (PLM) or nothing (DC).
+// push(ak, a) takes the value of plane k (read back from the staged plane, so it is not
+// carried in registers) and the value of plane k + AHEAD, and returns the two states on
+// the face k - 1/2.
 template <int RECON, class R>
 struct ZPipe;
 
@@ -150,14 +152,16 @@ struct ZPipe<0, R> {
     static constexpr int AHEAD = 0, PRIME = 1;  // plane k0-1 before the march
     R prev;
     __device__ void prime(const R* a) { prev = a[0]; }
-    __device__ void push(R a, R& aL, R& aR)
+    __device__ void push(R ak, R, R& aL, R& aR)
     {
         aL = prev;
-        aR = a;
-        prev = a;
+        aR = ak;
+        prev = ak;
     }
 };
 
+// (PLM keeps its own copy of a(k): reading it back from the staged plane was measured
+// slightly slower for this short pipeline.)
 template <class R>
 struct ZPipe<1, R> {
     static constexpr int AHEAD = 1, PRIME = 3;  // planes k0-2 .. k0
@@ -168,7 +172,7 @@ struct ZPipe<1, R> {
         am = a[1];
         a0 = a[2];
     }
-    __device__ void push(R a, R& aL, R& aR)
+    __device__ void push(R, R a, R& aL, R& aR)
     {
         const R d = slope_vl(am, a0, a);
         aL = apl;
@@ -182,7 +186,7 @@ struct ZPipe<1, R> {
 template <class R>
 struct ZPipe<2, R> {
     static constexpr int AHEAD = 2, PRIME = 5;  // planes k0-3 .. k0+1
-    R a0, a1, m0, ilo, apl;  // a(k), a(k+1), slope(k), a_{k-1/2}, a_+(k-1)
+    R a1, m0, ilo, apl;  // a(k+1), slope(k), a_{k-1/2}, a_+(k-1)
     __device__ void prime(const R* a)
     {
         const R s1 = cw_slope(a[0], a[1], a[2]);
@@ -193,21 +197,19 @@ struct ZPipe<2, R> {
         ilo = hi;
         cw_limit(a[2], lo, hi);                   // cell k0-1
         apl = hi;
-        a0 = a[3];
         a1 = a[4];
         m0 = s3;
     }
-    __device__ void push(R a, R& aL, R& aR)
+    __device__ void push(R ak, R a, R& aL, R& aR)
     {
-        const R m1 = cw_slope(a0, a1, a);         // slope of cell k+1
+        const R m1 = cw_slope(ak, a1, a);         // slope of cell k+1
         R lo = ilo;
-        R hi = cw_interface(a0, a1, m0, m1);      // a_{k+1/2}
+        R hi = cw_interface(ak, a1, m0, m1);      // a_{k+1/2}
         ilo = hi;
-        cw_limit(a0, lo, hi);                     // cell k
+        cw_limit(ak, lo, hi);                     // cell k
         aL = apl;
         aR = lo;
         apl = hi;
-        a0 = a1;
         a1 = a;
         m0 = m1;
     }
@@ -263,8 +265,9 @@ struct FluxTile {
                 sw[0][r][cc] = w.d; sw[1][r][cc] = w.vx; sw[2][r][cc] = w.vy; sw[3][r][cc] = w.vz;
                 sw[4][r][cc] = w.p; sw[5][r][cc] = w.bx; sw[6][r][cc] = w.by; sw[7][r][cc] = w.bz;
             }
-            // newest plane of the z pipeline
-            const Prim8<R> wz = load_prims(g, P, U, ic, jc, wrap_any(k + Pipe::AHEAD, g.nz));
+            // newest plane of the z pipeline (donor cell needs none beyond the staged one)
+            Prim8<R> wz{};
+            if constexpr (Pipe::AHEAD > 0) wz = load_prims(g, P, U, ic, jc, wrap_any(k + Pipe::AHEAD, g.nz));
             __syncthreads();
 
             const unsigned int c = (unsigned int)k * plane + (unsigned int)jc * g.nx + ic;
@@ -272,13 +275,16 @@ struct FluxTile {
             Prim7<R> L, Rt;
             Flux7<R> f;
             // ---- z faces from the pipeline: (rho, vz, vx, vy, p, Bx, By)
-            zp[0].push(wz.d, L.d, Rt.d);
-            zp[1].push(wz.vz, L.vn, Rt.vn);
-            zp[2].push(wz.vx, L.vt1, Rt.vt1);
-            zp[3].push(wz.vy, L.vt2, Rt.vt2);
-            zp[4].push(wz.p, L.p, Rt.p);
-            zp[5].push(wz.bx, L.bt1, Rt.bt1);
-            zp[6].push(wz.by, L.bt2, Rt.bt2);
+            {
+                const int r0 = row + SL, c0 = lane + SL;
+                zp[0].push(sw[0][r0][c0], wz.d, L.d, Rt.d);
+                zp[1].push(sw[3][r0][c0], wz.vz, L.vn, Rt.vn);
+                zp[2].push(sw[1][r0][c0], wz.vx, L.vt1, Rt.vt1);
+                zp[3].push(sw[2][r0][c0], wz.vy, L.vt2, Rt.vt2);
+                zp[4].push(sw[4][r0][c0], wz.p, L.p, Rt.p);
+                zp[5].push(sw[5][r0][c0], wz.bx, L.bt1, Rt.bt1);
+                zp[6].push(sw[6][r0][c0], wz.by, L.bt2, Rt.bt2);
+            }
             if (live) {
                 solve<RS>(L, Rt, ldT(U.b[2], c), P, f);
                 stT(Fo[14], c, f.d); stT(Fo[17], c, f.mn); stT(Fo[15], c, f.mt1); stT(Fo[16], c, f.mt2);

@@ -578,7 +578,7 @@ struct CtTile {
                     const double bz = 0.5 * ((double)b3 + (double)b3c);
                     double d = o[0];
                     if (d < P.rho_floor) d = P.rho_floor;
-                    const double id = 1.0 / d;
+                    const double id = rcp(d);
                     const double v[3] = {(double)o[1] * id, (double)o[2] * id, (double)o[3] * id};
                     const double ke = 0.5 * d * ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
                     const double b2s = (bx * bx + by * by) + bz * bz;
@@ -588,7 +588,7 @@ struct CtTile {
     #pragma unroll
                     for (int q = 0; q < 3; ++q) {
                         const double cf = fast_speed(P.gamma, d, pr, b2s, bd[q]);
-                        vmin = min_nan(vmin, g.dx[q] / (fabs(v[q]) + cf));
+                        vmin = min_nan(vmin, div_r(g.dx[q], fabs(v[q]) + cf));
                     }
                 }
                 // out never aliases in or base (the host rotates three registers)

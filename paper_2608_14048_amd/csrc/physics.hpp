@@ -8,7 +8,8 @@
 //
 // Every function is templated on the real type R: double for the FP64 path, float for
 // the FP32-bulk path (where reciprocals and square roots use the single-instruction
-// hardware approximations; FP64 keeps IEEE division and square root).
+// hardware approximations; FP64 refines the hardware estimates to within about an ulp
+// of the IEEE results).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,9 +37,28 @@ struct Flux4 {
 // scalar helpers per precision
 // ----------------------------------------------------------------------------------
 
-__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+// FP64 1/x for finite, normal x != 0: the hardware estimate refined by two
+// Newton-Raphson steps r <- r + r (1 - x r), each squaring the relative error.
+__device__ __forceinline__ double rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+    return __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+}
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
+// FP64 square root of a finite x >= 0: Goldschmidt's coupled iteration on the hardware
+// estimate y of 1/sqrt(x) (g = x y -> sqrt(x), h = y/2 -> 1/(2 sqrt(x))), then one
+// correction with the exact residual x - g^2.  x = 0 gives 0; x < 0 gives NaN.
+__device__ __forceinline__ double sqrt_r(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double t = __builtin_fma(-g, h, 0.5);
+    g = __builtin_fma(g, t, g);
+    h = __builtin_fma(h, t, h);
+    g = __builtin_fma(__builtin_fma(-g, g, x), h, g);
+    return x == 0.0 ? 0.0 : g;
+}
 __device__ __forceinline__ float sqrt_r(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double abs_r(double x) { return fabs(x); }
 __device__ __forceinline__ float abs_r(float x) { return fabsf(x); }
@@ -50,8 +70,16 @@ __device__ __forceinline__ float max_r(float a, float b) { return fmaxf(a, b); }
 // rounding of a helper does not depend on where the compiler inlines it)
 __device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-// a / b: IEEE division in FP64, a times the hardware reciprocal in FP32
-__device__ __forceinline__ double div_r(double a, double b) { return a / b; }
+// a / b for finite, normal b != 0.  FP64: the hardware reciprocal refined by one
+// Newton-Raphson step, then one correction of the quotient with the exact residual
+// a - b q (Markstein's scheme); FP32: a times the hardware reciprocal.
+__device__ __forceinline__ double div_r(double a, double b)
+{
+    double r = __builtin_amdgcn_rcp(b);
+    r = __builtin_fma(__builtin_fma(-b, r, 1.0), r, r);
+    const double q = a * r;
+    return __builtin_fma(__builtin_fma(-b, q, a), r, q);
+}
 __device__ __forceinline__ float div_r(float a, float b) { return a * rcp(b); }
 
 // ----------------------------------------------------------------------------------

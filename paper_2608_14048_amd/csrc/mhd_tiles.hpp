@@ -222,6 +222,9 @@ template <int RECON, int RS, class R, int TX, int TY>
 struct FluxTile {
     static constexpr int SL = Stencil<RECON>::L, SR = Stencil<RECON>::R;
     static constexpr int LX = TX + SL + SR, LY = TY + SL + SR;
+    // FP64 PPM: keep the compiler from hoisting the stencil loads of every variable
+    // ahead of the reconstructions (it would hold them all in registers at once)
+    static constexpr bool kFence = RECON == 2 && sizeof(R) == 8;
     struct Lds {
         R sw[8][LY][LX];
     };
@@ -289,6 +292,7 @@ struct FluxTile {
                 solve<RS>(L, Rt, ldT(U.b[2], c), P, f);
                 stT(Fo[14], c, f.d); stT(Fo[17], c, f.mn); stT(Fo[15], c, f.mt1); stT(Fo[16], c, f.mt2);
                 stT(Fo[18], c, f.e); stT(Fo[19], c, f.bt2); stT(Fo[20], c, -f.bt1);
+                if constexpr (kFence) __builtin_amdgcn_sched_barrier(0);
                 // ---- x faces: (rho, vx, vy, vz, p, By, Bz)
                 {
                     const int comp[7] = {0, 1, 2, 3, 4, 6, 7};
@@ -299,10 +303,12 @@ struct FluxTile {
     #pragma unroll
                         for (int s = -SL; s <= SR; ++s) st[3 + s] = sw[comp[v]][row + SL][lane + SL + s];
                         face_states<RECON>(st, *lr[v][0], *lr[v][1]);
+                        if constexpr (kFence) __builtin_amdgcn_sched_barrier(0);
                     }
                     solve<RS>(L, Rt, ldT(U.b[0], c), P, f);
                     stT(Fo[0], c, f.d); stT(Fo[1], c, f.mn); stT(Fo[2], c, f.mt1); stT(Fo[3], c, f.mt2);
                     stT(Fo[4], c, f.e); stT(Fo[5], c, f.bt2); stT(Fo[6], c, -f.bt1);
+                    if constexpr (kFence) __builtin_amdgcn_sched_barrier(0);
                 }
                 // ---- y faces: (rho, vy, vz, vx, p, Bz, Bx)
                 {
@@ -314,6 +320,7 @@ struct FluxTile {
     #pragma unroll
                         for (int s = -SL; s <= SR; ++s) st[3 + s] = sw[comp[v]][row + SL + s][lane + SL];
                         face_states<RECON>(st, *lr[v][0], *lr[v][1]);
+                        if constexpr (kFence) __builtin_amdgcn_sched_barrier(0);
                     }
                     solve<RS>(L, Rt, ldT(U.b[1], c), P, f);
                     stT(Fo[7], c, f.d); stT(Fo[9], c, f.mn); stT(Fo[10], c, f.mt1); stT(Fo[8], c, f.mt2);

@@ -109,8 +109,16 @@ __device__ __forceinline__ R cw_slope(R am, R a0, R ap)
     const R dm = a0 - am, dp = ap - a0;
     if (!(dm * dp > R(0))) return R(0);
     const R c = R(0.5) * (ap - am);
-    const R lim = min_r(abs_r(c), min_r(R(2) * abs_r(dm), R(2) * abs_r(dp)));
-    return c > R(0) ? lim : -lim;
+    if constexpr (sizeof(R) == 8) {
+        // dm and dp share a sign here, so c = (dm + dp)/2 is nonzero and carries it; the
+        // doubling is exact, so 2 min(|dm|, |dp|) = min(2|dm|, 2|dp|) bit for bit (the
+        // same values in fewer FP64 instructions; FP32 compiles shorter the other way)
+        const R lim = min_r(abs_r(c), R(2) * min_r(abs_r(dm), abs_r(dp)));
+        return __builtin_copysign(lim, c);
+    } else {
+        const R lim = min_r(abs_r(c), min_r(R(2) * abs_r(dm), R(2) * abs_r(dp)));
+        return c > R(0) ? lim : -lim;
+    }
 }
 
 // Colella-Woodward interface value between cells a0 and a1 from their limited slopes

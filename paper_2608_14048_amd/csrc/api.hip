@@ -70,11 +70,12 @@ struct Layout {
     size_t reg, nreg, F, Rc, partial, scalars, total;
 };
 
-// z planes per workgroup of the MHD kernels: about 2048 workgroups on large grids.
+// z planes per workgroup of the MHD kernels: about 3072 workgroups on large grids, four
+// full rounds of the 768 that the FP64 PPM flux kernel keeps resident (three per CU).
 int choose_kz(const mhd_grid* g)
 {
     const long long tiles = (long long)((g->nx + 63) / 64) * ((g->ny + 3) / 4);
-    const long long want = (2048 + tiles - 1) / tiles;
+    const long long want = (3072 + tiles - 1) / tiles;
     int kz = (int)((g->nz + want - 1) / want);
     if (kz < 4) kz = 4;
     if (kz > g->nz) kz = g->nz;

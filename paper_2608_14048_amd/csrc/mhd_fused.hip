@@ -23,16 +23,17 @@ constexpr int TY2 = 8;   // waves along y (CT/update kernel)
 
 // The FP64 PPM flux kernel is held to 168 registers, three waves per SIMD (the
 // workgroup memory of three workgroups fits a CU); its natural allocation gives two,
-// measured about 5 % slower.  Every other form keeps the compiler's choice.
+// measured about 8 % slower.  Every other form keeps the compiler's choice (the same
+// request spills more there and measured slower).
 template <int RECON, class R>
 struct FluxWaves {
     static constexpr int min = RECON == 2 && sizeof(R) == 8 ? 3 : 1;
 };
 
 template <int RECON, int RS, class R>
-__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(FluxWaves<RECON, R>::min))) void k_flux3(Geo g, MhdParams P, RegView<R> U, R* __restrict__ F,
-                                                 R* __restrict__ Rc, int kz, unsigned int ntx,
-                                                 unsigned int nty, unsigned int nblk)
+__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(FluxWaves<RECON, R>::min)))
+void k_flux3(Geo g, MhdParams P, RegView<R> U, R* __restrict__ F, R* __restrict__ Rc, int kz,
+             unsigned int ntx, unsigned int nty, unsigned int nblk)
 {
     using Tile = FluxTile<RECON, RS, R, TX, TY>;
     __shared__ typename Tile::Lds lds;

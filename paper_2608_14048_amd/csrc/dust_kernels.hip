@@ -73,29 +73,6 @@ __device__ __forceinline__ void st(T* base, unsigned int idx, T v)
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (unsigned int)sizeof(T)) = v;
 }
 
-// a / b for finite b != 0: the hardware reciprocal refined by one Newton step, then one
-// residual correction of the quotient (within an ulp of the IEEE quotient for normal
-// operands; six instructions instead of the scaled IEEE sequence).
-__device__ __forceinline__ double div_nr(double a, double b)
-{
-    double r = __builtin_amdgcn_rcp(b);
-    r = fma(fma(-b, r, 1.0), r, r);
-    const double q = a * r;
-    return fma(fma(-b, q, a), r, q);
-}
-// FP32: the hardware reciprocal (one ulp) times a
-__device__ __forceinline__ float div_nr(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-
-// van Leer's harmonic-mean slope (the same formula as the shared helper, with div_nr:
-// the denominator is a sum of two numbers of one sign, never zero here).
-template <class R>
-__device__ __forceinline__ R slope_hm(R am, R a0, R ap)
-{
-    const R dm = a0 - am, dp = ap - a0;
-    const R pr = dm * dp;
-    return pr > R(0) ? div_nr(R(2) * pr, dm + dp) : R(0);
-}
-
 // Halo (cells on each side) of the reconstruction when both faces of a cell are built.
 template <int RECON>
 struct Halo {
@@ -110,9 +87,9 @@ __device__ __forceinline__ void both_faces(const R* a, R& loL, R& loR, R& hiL, R
     if constexpr (RECON == 0) {
         loL = a[0]; loR = a[1]; hiL = a[1]; hiR = a[2];
     } else {
-        const R sm = slope_hm(a[0], a[1], a[2]);
-        const R s0 = slope_hm(a[1], a[2], a[3]);
-        const R sp = slope_hm(a[2], a[3], a[4]);
+        const R sm = slope_vl(a[0], a[1], a[2]);
+        const R s0 = slope_vl(a[1], a[2], a[3]);
+        const R sp = slope_vl(a[2], a[3], a[4]);
         loL = a[1] + R(0.5) * sm;
         loR = a[2] - R(0.5) * s0;
         hiL = a[2] + R(0.5) * s0;
@@ -177,13 +154,13 @@ struct ZLine<1, R> {
     R am, a0, apl;  // a(m-1), a(m), high-side state of cell m-1
     __device__ void prime(const R* a)
     {
-        apl = a[1] + R(0.5) * slope_hm(a[0], a[1], a[2]);
+        apl = a[1] + R(0.5) * slope_vl(a[0], a[1], a[2]);
         am = a[1];
         a0 = a[2];
     }
     __device__ void push(R a, R& aL, R& aR)
     {
-        const R d = slope_hm(am, a0, a);
+        const R d = slope_vl(am, a0, a);
         aL = apl;
         aR = a0 - R(0.5) * d;
         apl = a0 + R(0.5) * d;

@@ -258,7 +258,10 @@ struct FluxTile {
         }
 
         for (int k = k0; k < k1; ++k) {
-            // stage the primitives of plane k (tile + x/y halos, corners skipped)
+            // stage the primitives of plane k (tile + x/y halos, corners skipped); the
+            // staging waves get issue priority so their loads go out ahead of the
+            // arithmetic of the other workgroups on the CU
+            __builtin_amdgcn_s_setprio(1);
             for (int q = threadIdx.x; q < LX * LY; q += TX * TY) {
                 const int r = q / LX, cc = q - r * LX;
                 const bool xh = cc < SL || cc >= SL + TX, yh = r < SL || r >= SL + TY;
@@ -272,6 +275,7 @@ struct FluxTile {
             Prim8<R> wz{};
             if constexpr (Pipe::AHEAD > 0) wz = load_prims(g, P, U, ic, jc, wrap_any(k + Pipe::AHEAD, g.nz));
             __syncthreads();
+            __builtin_amdgcn_s_setprio(0);
 
             const unsigned int c = (unsigned int)k * plane + (unsigned int)jc * g.nx + ic;
             R st[6];

@@ -133,6 +133,31 @@ def test_dt_cfl_parity(case):
         pr.close()
 
 
+def test_degenerate_fast_speed():
+    """A uniform state whose sound speed equals the Alfven speed along x: the fast-speed
+    discriminant is exactly zero on every x face and in the time step (gamma = 2,
+    rho = 1, p = 1/2, B = (1, 0, 0)), and the HLLD star denominators vanish.  The state
+    must stay uniform, finite and equal to the oracle's."""
+    shape = (16, 8, 8)
+    full = (shape[2], shape[1], shape[0])
+    one, zero = np.ones(full), np.zeros(full)
+    st = I.mhd_state(one, zero, zero, zero, 0.5 * one, one, zero, zero)
+    pr = Pair(shape, gamma=2.0, recon="ppm")
+    try:
+        pr.sim.set_state(st)
+        g = pr.sim.dt_cfl()
+        o = oracle.dt_cfl(pr.cfg, st)
+        _say(f"  degenerate: dt gpu {g!r} oracle {o!r}")
+        assert np.isfinite(g) and abs(g - o) <= 1e-14 * o
+        ref = oracle.step(pr.cfg, st, o)
+        pr.sim.step(o)
+        got = pr.sim.state()
+        assert_close(pr, got, ref, STEP_TOL, "degenerate fast speed")
+        assert np.abs(got - st).max() <= 1e-14
+    finally:
+        pr.close()
+
+
 # ----------------------------------------------------------------------------------
 # one step from the same input
 # ----------------------------------------------------------------------------------

@@ -447,7 +447,7 @@ static void mhd_work_free(mhd_work* W)
     }
 }
 
-/* Conserved -> primitive with the density and pressure floors (Sec. "Newtonian MHD"):
+/* Conserved -> primitive with the density and pressure floors (Sec. "Newtonian Magnetohydrodynamics"):
  * B_cc is the mean of the two bounding face values (Sec. "Constrained Transport"),
  * p = (gamma-1)(E - rho v^2/2 - B^2/2).  The floors act on the primitives only. */
 static void mhd_prims(const orc_cfg* c, mhd_work* W)
@@ -754,8 +754,9 @@ static void dust_explicit_rhs(const orc_cfg* c, const double* state, double* dud
 }
 
 /* Drag rates G(u) on the momenta, eq. (dust_momentum) and its reaction on the gas:
- * species k: rho_k (v - v_k)/t_k; gas: -sum_k rho_k (v - v_k)/t_k.  Densities are
- * unchanged by drag. */
+ * species k: rho_k (v - v_k)/t_k = (rho_k v - p_k)/t_k, written with the species
+ * momentum p_k so that it is the linear map of the momenta that the implicit solve
+ * inverts; gas: minus the sum over species.  Densities are unchanged by drag. */
 static void dust_drag_rate(const orc_cfg* c, const double* state, double* G)
 {
     long nc = (long)c->nx * c->ny * c->nz;
@@ -766,12 +767,10 @@ static void dust_drag_rate(const orc_cfg* c, const double* state, double* G)
         double wg[4];
         fluid_prims(c, 0, &state[ci], &state[nc + ci], &state[2 * nc + ci], &state[3 * nc + ci], wg);
         for (int s = 1; s < nf; ++s) {
-            double wd[4];
-            const double* base = state + 4 * s * nc;
-            fluid_prims(c, s, &base[ci], &base[nc + ci], &base[2 * nc + ci], &base[3 * nc + ci], wd);
             double rk = state[4 * s * nc + ci];
             for (int a = 0; a < 3; ++a) {
-                double fk = rk * (wg[1 + a] - wd[1 + a]) / c->tstop[s - 1];
+                double pk = state[(4 * s + 1 + a) * nc + ci];
+                double fk = (rk * wg[1 + a] - pk) / c->tstop[s - 1];
                 G[(4 * s + 1 + a) * nc + ci] += fk;
                 G[(1 + a) * nc + ci] -= fk;
             }
@@ -844,11 +843,32 @@ static void dust_drag_stage(const orc_cfg* c, double* state, double h)
     }
 }
 
+/* The dust floor of Sec. "Multifluid Dust": a species whose density is below the floor
+ * is reset to the floor with zero velocity.  Reading: the reset rewrites the state a
+ * step starts from (the gas density floor only limits the primitives).  Inside the
+ * step a species that stage 1 drives below the floor is converted to primitives as the
+ * floor at rest (fluxes, time step) but not rewritten, because the drag rate of the
+ * stage-1 state is the one its implicit solve used. */
+static void dust_floor_reset(const orc_cfg* c, double* state)
+{
+    long nc = (long)c->nx * c->ny * c->nz;
+    for (int s = 1; s <= c->ndust; ++s) {
+        double* rho = state + 4 * s * nc;
+#pragma omp parallel for
+        for (long ci = 0; ci < nc; ++ci)
+            if (rho[ci] < c->dust_rho_floor) {
+                rho[ci] = c->dust_rho_floor;
+                for (int a = 1; a <= 3; ++a) rho[a * nc + ci] = 0.0;
+            }
+    }
+}
+
 /* IMEX2P: ARS(2,2,2) with the diagonal weight lambda = 1 + 1/sqrt(2) (Sec. "Time
  * Integration") and the explicit weight delta = 1 - 1/(2 lambda):
  *   U1      = u + lambda dt F(u) + lambda dt G(U1)
  *   u_new   = u + dt [delta F(u) + (1-delta) F(U1)] + dt [(1-lambda) G(U1) + lambda G(u_new)]
- * Each implicit stage is the drag solve S_h with h = lambda dt. */
+ * Each implicit stage is the drag solve S_h with h = lambda dt.  The state u passes the
+ * dust floor reset first. */
 static void imex2p_step(const orc_cfg* c, double* state, double dt)
 {
     long len = orc_state_len(c);
@@ -858,6 +878,7 @@ static void imex2p_step(const orc_cfg* c, double* state, double dt)
     double* F1 = zalloc(len);
     double* G1 = zalloc(len);
     double* U1 = zalloc(len);
+    dust_floor_reset(c, state);
     dust_explicit_rhs(c, state, Fn);
     for (long e = 0; e < len; ++e) U1[e] = state[e] + (lam * dt) * Fn[e];
     dust_drag_stage(c, U1, lam * dt);

@@ -760,3 +760,189 @@ def test_cfl_uses_largest_characteristic_speed():
         for d in range(3):
             best = min(best, np.min(0.5 / (np.abs(s[4 * f + 1 + d] / r) + (1.0 if f == 0 else 0.0))))
     assert abs(oracle.dt_cfl(c, st) - 0.3 / (1 + 1 / math.sqrt(2)) * best) < 1e-14
+
+
+# ----------------------------------------------------------------------------------
+# Gardiner-Stone edges at zero mass flux; the dust floor; the isothermal gas solver
+# ----------------------------------------------------------------------------------
+
+def _x_mirror_state(shape, seed):
+    """A state that is its own mirror image under x -> -x (cell i <-> nx-1-i): uniform
+    density, pressure and B_x, no B_y, B_z, no v_x, and random v_y, v_z that are even in
+    x.  Every x-face mass flux of a first stage is then exactly zero, so the edge EMFs
+    E_y and E_z take the zero-mass-flux branch of the Gardiner-Stone average on every
+    x face."""
+    nx, ny, nz = shape
+    assert nx % 2 == 0
+    rng = np.random.default_rng(seed)
+    full = (nz, ny, nx)
+
+    def even(a):
+        a[..., nx // 2:] = a[..., : nx // 2][..., ::-1]
+        return a
+
+    vy = even(rng.normal(0.0, 0.5, full))
+    vz = even(rng.normal(0.0, 0.5, full))
+    one, zero = np.ones(full), np.zeros(full)
+    return I.mhd_state(one, zero, vy, vz, 0.6 * one / (2.0 / 3.0), 0.8 * one, zero, zero)
+
+
+def x_mirror_broken(s, shape):
+    """Names of the fields of s that are not exact mirror images of themselves under
+    x -> -x, with B an axial vector (B_x even, B_y and B_z odd; v_x odd)."""
+    nx, ny, nz = shape
+    f = s.reshape(8, nz, ny, nx)
+    cell = lambda a: a[..., ::-1]
+    face = lambda a: np.roll(a[..., ::-1], 1, axis=-1)  # face f <-> face nx - f
+    checks = {"rho": (f[0], cell(f[0])), "Mx": (f[1], -cell(f[1])), "My": (f[2], cell(f[2])),
+              "Mz": (f[3], cell(f[3])), "E": (f[4], cell(f[4])), "b1": (f[5], face(f[5])),
+              "b2": (f[6], -cell(f[6])), "b3": (f[7], -cell(f[7]))}
+    return [k for k, (a, b) in checks.items() if not np.array_equal(a, b)]
+
+
+@pytest.mark.parametrize("integ,recon", [("euler1", "plm"), ("euler1", "dc"), ("vl2", "plm")])
+def test_zero_mass_flux_edges_keep_mirror_symmetry(integ, recon):
+    """With every x-face mass flux exactly zero (HLLE on a state with no v_x and uniform
+    density, pressure and B_x) the Gardiner-Stone corrections across x faces must not
+    prefer either side: a mirror-symmetric state stays mirror-symmetric in every bit.
+    Taking either one-sided candidate at zero flux breaks the symmetry.  (The first
+    stage of each integrator has zero x mass flux on every face; PPM is left out
+    because its interface average is not a bitwise mirror-symmetric expression.)"""
+    shape = (16, 10, 6)
+    st = _x_mirror_state(shape, 11)
+    assert x_mirror_broken(st, shape) == []
+    c = oracle.make_cfg(shape, length=(1.0, 10 / 16, 6 / 16), recon=recon, riemann="hlle",
+                        integ=integ)
+    dt = oracle.dt_cfl(c, st)
+    s = oracle.step(c, st, dt)
+    assert x_mirror_broken(s, shape) == []
+    # the step is not trivial: the field lines bend and b_y grows
+    assert np.abs(s.reshape(8, -1)[6]).max() > 1e-4
+
+
+def test_dust_floor_resets_a_species_to_the_floor_at_rest():
+    """Sec. "Multifluid Dust": a species below the dust floor is reset to the floor with
+    zero velocity.  A uniform species below the floor, moving through gas and dust at
+    rest, comes out of one step as exactly the floor at rest; nothing else moves."""
+    shape = (6, 5, 4)
+    full = (4, 5, 6)
+    floor = 1e-6
+    one, zero = np.ones(full), np.zeros(full)
+    st = I.dust_state([(one, zero, zero, zero), (0.4 * floor * one, 0.3 * one, -0.2 * one, 0.1 * one),
+                       (0.01 * one, zero, zero, zero)])
+    c = oracle.make_cfg(shape, eos="isothermal_hydro", tstop=(0.1, 1.0), dust_rho_floor=floor,
+                        recon="plm", riemann="hlle", integ="imex2p")
+    s = oracle.step(c, st, 1e-3).reshape(12, -1)
+    st = st.reshape(12, -1)
+    assert np.all(s[4] == floor)
+    assert np.all(s[5:8] == 0.0)
+    assert np.array_equal(s[:4], st[:4]) and np.array_equal(s[8:], st[8:])
+
+
+def test_dust_floor_reset_acts_on_the_step_input():
+    """The reset rewrites the state a step starts from: a step from a state with sub-floor
+    cells equals, bit for bit, the step from that state with those cells already reset;
+    and an evacuated region moving fast does not bind the time step."""
+    shape = (12, 10, 8)
+    st, ts = I.dust_drift(shape=shape, nd=3, seed=4, noise=1e-2)
+    nc = int(np.prod(shape))
+    f = st.reshape(-1, nc).copy()
+    floor = 1e-5
+    rng = np.random.default_rng(5)
+    low = rng.random(nc) < 0.3
+    f[4][low] = floor * rng.uniform(0.0, 0.9, low.sum())      # species 1 below the floor
+    f[5][low] = 50.0 * f[4][low]                                # moving fast (v_x = 50)
+    st = f.ravel()
+    reset = f.copy()
+    reset[4][low] = floor
+    reset[5:8, low] = 0.0
+    c = oracle.make_cfg(shape, eos="isothermal_hydro", tstop=tuple(ts), dust_rho_floor=floor,
+                        gacc=(0.05, 0, 0), recon="plm", riemann="hlle", integ="imex2p")
+    dt = oracle.dt_cfl(c, st)
+    assert dt == oracle.dt_cfl(c, reset.ravel())
+    assert np.array_equal(oracle.step(c, st, dt), oracle.step(c, reset.ravel(), dt))
+    # without the reset the fast sub-floor cells would move their momentum along
+    assert not np.array_equal(oracle.step(c, st, dt).reshape(-1, nc)[5][low], f[5][low])
+
+
+def _iso_tube(n, left, right):
+    """Isothermal shock tube on the doubled periodic domain [-1, 1) along x: the left
+    state for |x| < 1/2, the right one elsewhere; one passive dust species (density
+    1e-9 at rest, stopping time 1e9) because the isothermal path carries dust."""
+    x = -1.0 + (np.arange(n) + 0.5) * (2.0 / n)
+    inside = np.abs(x) < 0.5
+    full = (1, 1, n)
+    rho = np.where(inside, left[0], right[0]).reshape(full)
+    u = np.where(inside, left[1], right[1]).reshape(full)
+    zero = np.zeros(full)
+    st = I.dust_state([(rho, u, zero, zero), (1e-9 + zero, zero, zero, zero)])
+    return st, x
+
+
+@pytest.mark.parametrize("left,right", [((1.0, 0.0), (0.25, 0.0)), ((1.0, 1.0), (1.0, -1.0))],
+                         ids=["rarefaction-shock", "two-shocks"])
+def test_isothermal_hlle_shock_tube_against_exact_solution(left, right):
+    """The isothermal HLLE gas flux through the whole step: density and velocity converge
+    to the exact isothermal Riemann solution (at t = 0.25, c_s = 0.8) at about first
+    order, and the shocks sit where the exact shock speeds put them."""
+    errs = []
+    cs = 0.8
+    rs, us = exact_riemann.iso_star_state(*left, *right, cs)
+    for n in (256, 512):
+        st, x = _iso_tube(n, left, right)
+        c = oracle.make_cfg((n, 1, 1), length=(2.0, 2.0 / n, 2.0 / n), eos="isothermal_hydro",
+                            cs=cs, tstop=(1e9,), recon="plm", riemann="hlle", integ="imex2p",
+                            courant=0.3)
+        t, s = 0.0, st.copy()
+        for _ in range(MAX_STEPS):
+            if t >= 0.25 - 1e-14:
+                break
+            dt = min(oracle.dt_cfl(c, s), 0.25 - t)
+            s = oracle.step(c, s, dt)
+            t += dt
+        assert t >= 0.25 - 1e-14, "step cap reached"
+        rho, u = s[:n], s[n:2 * n] / s[:n]
+        sel = (x > 0.0) & (x < 1.0)
+        dx = 2.0 / n
+        edges = np.concatenate([x[sel] - 0.5 * dx, [x[sel][-1] + 0.5 * dx]])
+        ex = exact_riemann.iso_cell_averages(edges, 0.25, 0.5, left, right, cs)
+        errs.append((np.mean(np.abs(rho[sel] - ex[0])), np.mean(np.abs(u[sel] - ex[1]))))
+        # right-moving shock: the last cell above the middle of the density jump
+        if rs > right[0]:
+            xs = 0.5 + 0.25 * (right[1] + cs * math.sqrt(rs / right[0]))
+            win = (x > 0.5) & (x < 1.0)
+            above = x[win][rho[win] > 0.5 * (rs + right[0])]
+            assert abs(above.max() - xs) < 3 * dx, (above.max(), xs)
+    assert errs[1][0] < 0.01 and errs[1][1] < 0.02, errs
+    assert errs[0][0] / errs[1][0] > 1.4 and errs[0][1] / errs[1][1] > 1.4, errs
+
+
+def test_isothermal_hlle_linear_acoustic_wave_matches_von_neumann_factor():
+    """On a gas at rest the isothermal HLLE bounds are -c_s and +c_s, so the flux of a
+    small acoustic perturbation is exact upwinding of each characteristic field (|A| =
+    c_s I for the linear system).  With donor cell and the explicit part of IMEX2P (a
+    two-stage second-order Runge-Kutta method: amplification 1 + z + z^2/2) a right-going
+    Fourier mode of wavenumber theta per cell is multiplied each step by R(z) with
+    z = -nu (1 - exp(-i theta)), nu = c_s dt/dx.  Any change to the wave-speed bounds, the
+    dissipation or the pressure term changes that factor."""
+    n, cs, eps, nsteps, mode = 32, 0.8, 1e-8, 20, 3
+    dx = 1.0 / n
+    j = np.arange(n)
+    theta = 2.0 * math.pi * mode / n
+    drho = eps * np.cos(theta * j)
+    full = (1, 1, n)
+    rho = (1.0 + drho).reshape(full)
+    u = (cs * drho / rho.ravel()).reshape(full)  # right-going: delta M = c_s delta rho
+    zero = np.zeros(full)
+    st = I.dust_state([(rho, u, zero, zero), (1e-9 + zero, zero, zero, zero)])
+    c = oracle.make_cfg((n, 1, 1), length=(1.0, dx, dx), eos="isothermal_hydro", cs=cs,
+                        tstop=(1e9,), recon="dc", riemann="hlle", integ="imex2p")
+    nu = 0.5
+    dt = nu * dx / cs
+    s, _ = oracle.run(c, st, nsteps, dts=[dt] * nsteps)
+    amp = 2.0 / n * np.sum((s[:n] - 1.0) * np.exp(-1j * theta * j))
+    z = -nu * (1.0 - np.exp(-1j * theta))
+    want = eps * (1.0 + z + 0.5 * z * z) ** nsteps
+    assert abs(amp - want) <= 1e-6 * eps, (amp, want)
+    # the mode really decayed and moved (not a trivial check)
+    assert abs(want) < 0.9 * eps and abs(np.angle(want)) > 0.5

@@ -52,7 +52,8 @@ typedef enum {
     MHD_E_UNSUPPORTED = -2, /* the scheme combination does not exist (mhd_create) */
     MHD_E_NOMEM = -3,       /* workspace smaller than mhd_workspace_bytes, or host alloc failed */
     MHD_E_DEVICE = -4,      /* a HIP runtime call failed */
-    MHD_E_NONFINITE = -5    /* the state holds NaN or Inf (found by the CFL reduction) */
+    MHD_E_NONFINITE = -5,   /* the state holds NaN or Inf (found by the CFL reduction) */
+    MHD_E_TOOBIG = -6       /* grid larger than the static scratch of mhd_dt_cfl_noalloc */
 } mhd_status;
 
 typedef enum { MHD_EOS_ADIABATIC_MHD = 0, MHD_EOS_ISOTHERMAL_HYDRO = 1 } mhd_eos;
@@ -154,6 +155,23 @@ mhd_status mhd_step(mhd_ctx* ctx, double dt);
  * double from the device (synchronises the stream).  MHD_E_NONFINITE if the state
  * holds NaN or Inf. */
 mhd_status mhd_dt_cfl(mhd_ctx* ctx, double* dt);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the Courant-limited step of
+ * mhd_dt_cfl for a canonical FP64 state that the caller holds on the device, with no
+ * context and no workspace.  grid, phys and scheme are validated as by mhd_create;
+ * state_device: the canonical state (mhd_state_len doubles), read only; dt_device: one
+ * double of device memory that receives C C_max min(...), or NaN if the state holds
+ * NaN or Inf.  Asynchronous on hip_stream, which must belong to the current device;
+ * no host synchronisation, no allocation, no memset (capturable in a HIP graph).  The
+ * per-workgroup partial minima live in a static device array of the library, one copy
+ * per GPU that holds it until the process ends: MHD_NOALLOC_MAX_CELLS cells at most
+ * (4 MiB of partials), larger grids return MHD_E_TOOBIG.  Every call on one GPU shares
+ * that array: calls that overlap on one GPU (other streams, other threads) race and
+ * must be serialised by the caller. */
+#define MHD_NOALLOC_MAX_CELLS (1LL << 27)
+mhd_status mhd_dt_cfl_noalloc(const mhd_grid* grid, const mhd_physics* phys, const mhd_scheme* scheme,
+                              const double* state_device, double* dt_device, void* hip_stream);
 
 /* Volume integrals and extrema of the current state, in FP64 with a fixed-order
  * (deterministic) reduction.  out must hold n >= 12 + ndust doubles:

@@ -23,7 +23,8 @@ INTEG = {"vl2": 0, "rk2": 1, "imex2p": 2, "euler1": 3}
 PREC = {"fp64": 0, "fp32_bulk": 1}
 
 STATUS = {0: "MHD_OK", -1: "MHD_E_INVAL", -2: "MHD_E_UNSUPPORTED", -3: "MHD_E_NOMEM",
-          -4: "MHD_E_DEVICE", -5: "MHD_E_NONFINITE"}
+          -4: "MHD_E_DEVICE", -5: "MHD_E_NONFINITE", -6: "MHD_E_TOOBIG"}
+NOALLOC_MAX_CELLS = 1 << 27
 
 
 class MhdError(RuntimeError):
@@ -72,6 +73,8 @@ def load_library(path: str = LIB_PATH):
     L.mhd_get_state.argtypes = [vp, vp, ctypes.c_int]
     L.mhd_step.argtypes = [vp, ctypes.c_double]
     L.mhd_dt_cfl.argtypes = [vp, dp]
+    L.mhd_dt_cfl_noalloc.argtypes = [ctypes.POINTER(MhdGrid), ctypes.POINTER(MhdPhysics),
+                                     ctypes.POINTER(MhdScheme), vp, vp, vp]
     L.mhd_diagnostics.argtypes = [vp, dp, ctypes.c_int]
     L.mhd_destroy.argtypes = [vp]
     L.mhd_destroy.restype = None
@@ -116,7 +119,7 @@ def load_library(path: str = LIB_PATH):
     L.mhd_cnn_destroy.argtypes = [vp]
     L.mhd_cnn_destroy.restype = None
     for name in ("mhd_workspace_bytes", "mhd_create", "mhd_state_len", "mhd_set_state",
-                 "mhd_get_state", "mhd_step", "mhd_dt_cfl", "mhd_diagnostics",
+                 "mhd_get_state", "mhd_step", "mhd_dt_cfl", "mhd_dt_cfl_noalloc", "mhd_diagnostics",
                  "mhd_timing_enable", "mhd_timing_read", "mhd_batch_workspace_bytes",
                  "mhd_batch_create", "mhd_batch_state_len", "mhd_batch_set_state",
                  "mhd_batch_get_state", "mhd_batch_step", "mhd_batch_dt_cfl",
@@ -220,6 +223,14 @@ def mhd_dt_cfl(ctx: int) -> float:
     out = ctypes.c_double(0.0)
     _check(load_library().mhd_dt_cfl(ctypes.c_void_p(ctx), ctypes.byref(out)), "mhd_dt_cfl")
     return out.value
+
+
+def mhd_dt_cfl_noalloc(grid: MhdGrid, phys: MhdPhysics, scheme: MhdScheme, state_ptr: int,
+                       dt_ptr: int, stream: int) -> None:
+    """Asynchronous CFL step of a device state into one device double (no workspace)."""
+    _check(load_library().mhd_dt_cfl_noalloc(ctypes.byref(grid), ctypes.byref(phys), ctypes.byref(scheme),
+                                             ctypes.c_void_p(state_ptr), ctypes.c_void_p(dt_ptr),
+                                             ctypes.c_void_p(stream)), "mhd_dt_cfl_noalloc")
 
 
 def mhd_diagnostics(ctx: int, n: int) -> np.ndarray:

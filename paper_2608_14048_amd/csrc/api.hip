@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -62,7 +63,44 @@ struct mhd_ctx {
     EventTimer* timer;
 };
 
+// Scratch of the allocation-free entry point mhd_dt_cfl_noalloc: the partial minima of
+// the CFL reduction, one per workgroup of 256 cells.  A static device array, so every
+// GPU the library runs on holds its own copy until the process ends.  Host code must
+// not take its name as a device address: the address of each device's copy is looked
+// up once per device (hipGetSymbolAddress with that device current) and kept here.
+static __device__ __align__(256) double scratch[MHD_NOALLOC_MAX_CELLS / kBlock];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch` (looked up on the first call on that device);
+// hipErrorInvalidValue if the stream belongs to another device.
+hipError_t noalloc_scratch(hipStream_t s, double** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    if (s) {
+        hipDevice_t sd = 0;
+        e = hipStreamGetDevice(s, &sd);
+        if (e != hipSuccess) return e;
+        if ((int)sd != dev) return hipErrorInvalidValue;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = (double*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -93,6 +131,31 @@ Geo make_geo(const mhd_grid* grid)
         g.inv_dx[a] = 1.0 / g.dx[a];
     }
     return g;
+}
+
+// Kernel parameters of a validated configuration; returns the factor C C_max of eq. (cfl).
+double make_params(const mhd_physics* phys, const mhd_scheme* scheme, MhdParams* mp, DustParams* dp)
+{
+    *mp = MhdParams{};
+    *dp = DustParams{};
+    mp->gamma = phys->gamma;
+    mp->gm1inv = 1.0 / (phys->gamma - 1.0);
+    mp->rho_floor = phys->rho_floor;
+    mp->p_floor = phys->p_floor;
+    // below single-precision round-off the HLLD degeneracy test would never fire
+    const bool fp32 = scheme->prec == MHD_PREC_FP32_BULK;
+    mp->hlld_eps = fp32 && scheme->hlld_eps < 1e-6 ? 1e-6 : scheme->hlld_eps;
+    dp->nd = phys->ndust;
+    dp->cs = phys->cs_iso;
+    dp->rho_floor = phys->rho_floor;
+    dp->dust_floor = phys->dust_rho_floor;
+    for (int a = 0; a < 3; ++a) {
+        mp->gacc[a] = phys->gas_accel[a];
+        dp->gacc[a] = phys->gas_accel[a];
+    }
+    for (int k = 0; k < phys->ndust; ++k) dp->ts[k] = phys->t_stop[k];
+    const double cmax = scheme->integ == MHD_INT_IMEX2P ? 1.0 / (1.0 + 1.0 / std::sqrt(2.0)) : 1.0;
+    return scheme->courant * cmax;
 }
 
 int state_fields(const mhd_physics* p)
@@ -299,6 +362,7 @@ const char* mhd_strerror(mhd_status s)
     case MHD_E_NOMEM: return "workspace too small or host allocation failed";
     case MHD_E_DEVICE: return "HIP runtime error";
     case MHD_E_NONFINITE: return "state holds NaN or Inf";
+    case MHD_E_TOOBIG: return "grid exceeds the static scratch of the allocation-free entry point";
     }
     return "unknown status";
 }
@@ -338,24 +402,8 @@ mhd_status mhd_create(const mhd_grid* grid, const mhd_physics* phys, const mhd_s
     c->geo = make_geo(grid);
     c->fg = fused_grid(c->geo, choose_kz(grid));
     c->dg = dust_grid(c->geo, 1 + (phys->eos == MHD_EOS_ADIABATIC_MHD ? 0 : phys->ndust));
-    c->mp.gamma = phys->gamma;
-    c->mp.gm1inv = 1.0 / (phys->gamma - 1.0);
-    c->mp.rho_floor = phys->rho_floor;
-    c->mp.p_floor = phys->p_floor;
     c->fp32 = scheme->prec == MHD_PREC_FP32_BULK;
-    // below single-precision round-off the HLLD degeneracy test would never fire
-    c->mp.hlld_eps = c->fp32 && scheme->hlld_eps < 1e-6 ? 1e-6 : scheme->hlld_eps;
-    c->dp.nd = phys->ndust;
-    c->dp.cs = phys->cs_iso;
-    c->dp.rho_floor = phys->rho_floor;
-    c->dp.dust_floor = phys->dust_rho_floor;
-    for (int a = 0; a < 3; ++a) {
-        c->mp.gacc[a] = phys->gas_accel[a];
-        c->dp.gacc[a] = phys->gas_accel[a];
-    }
-    for (int k = 0; k < phys->ndust; ++k) c->dp.ts[k] = phys->t_stop[k];
-    const double cmax = scheme->integ == MHD_INT_IMEX2P ? 1.0 / (1.0 + 1.0 / std::sqrt(2.0)) : 1.0;
-    c->cfl_scale = scheme->courant * cmax;
+    c->cfl_scale = make_params(phys, scheme, &c->mp, &c->dp);
 
     char* base = (char*)device_workspace;
     for (size_t r = 0; r < 3; ++r) {
@@ -513,6 +561,29 @@ mhd_status mhd_timing_read(mhd_ctx* c, double* ms, int* launches, int nslot)
 }
 
 const char* mhd_timing_name(int q) { return (q >= 0 && q < T_NSLOT) ? kSlotNames[q] : nullptr; }
+
+mhd_status mhd_dt_cfl_noalloc(const mhd_grid* grid, const mhd_physics* phys, const mhd_scheme* scheme,
+                              const double* state_device, double* dt_device, void* hip_stream)
+{
+    if (!state_device || !dt_device) return MHD_E_INVAL;
+    mhd_status st = validate(grid, phys, scheme);
+    if (st != MHD_OK) return st;
+    const long long n = (long long)grid->nx * grid->ny * grid->nz;
+    if (n > MHD_NOALLOC_MAX_CELLS) return MHD_E_TOOBIG;
+    const hipStream_t s = (hipStream_t)hip_stream;
+    double* partial = nullptr;
+    const hipError_t es = noalloc_scratch(s, &partial);
+    if (es == hipErrorInvalidValue) return MHD_E_INVAL;
+    if (es != hipSuccess) return MHD_E_DEVICE;
+    MhdParams mp;
+    DustParams dp;
+    const double scale = make_params(phys, scheme, &mp, &dp);
+    const Geo g = make_geo(grid);
+    hipError_t e = phys->eos == MHD_EOS_ADIABATIC_MHD
+                       ? launch_cfl_mhd(g, mp, state_device, partial, dt_device, scale, s)
+                       : launch_cfl_dust(g, dp, state_device, partial, dt_device, scale, s);
+    return dev(e);
+}
 
 void mhd_destroy(mhd_ctx* c)
 {

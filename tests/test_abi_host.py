@@ -156,3 +156,20 @@ def test_closure_validation_before_touching_the_device():
     with pytest.raises(B.MhdError) as e:
         B.mhd_cnn_create(g64, phys, fake + 8, nb, 0)
     assert e.value.code == -1
+
+
+def test_noalloc_entry_point_rejects_before_any_launch():
+    """mhd_dt_cfl_noalloc validates like mhd_create and refuses grids beyond its static
+    scratch before touching the device (the pointers here are never dereferenced)."""
+    lib = B.load_library()
+    fake = ctypes.c_void_p(0x1000)
+    g, p, s = _ws()
+    assert lib.mhd_dt_cfl_noalloc(ctypes.byref(g), ctypes.byref(p), ctypes.byref(s), None, fake, None) == -1
+    assert lib.mhd_dt_cfl_noalloc(ctypes.byref(g), ctypes.byref(p), ctypes.byref(s), fake, None, None) == -1
+    g0, p0, s0 = _ws((0, 8, 8))
+    assert lib.mhd_dt_cfl_noalloc(ctypes.byref(g0), ctypes.byref(p0), ctypes.byref(s0), fake, fake, None) == -1
+    gd, pd, sd = _ws(eos="isothermal_hydro", tstop=(1.0,), integ="vl2", riemann="hlle")
+    assert lib.mhd_dt_cfl_noalloc(ctypes.byref(gd), ctypes.byref(pd), ctypes.byref(sd), fake, fake, None) == -2
+    gb, pb, sb = _ws((1024, 1024, 256))
+    assert lib.mhd_dt_cfl_noalloc(ctypes.byref(gb), ctypes.byref(pb), ctypes.byref(sb), fake, fake, None) == -6
+    assert B.NOALLOC_MAX_CELLS == 1 << 27

@@ -66,6 +66,7 @@ def _lib():
         dp = ctypes.POINTER(ctypes.c_double)
         cp = ctypes.POINTER(OrcCfg)
         L.orc_num_threads.argtypes = []; L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]; L.orc_set_num_threads.restype = None
         L.orc_state_len.argtypes = [cp]; L.orc_state_len.restype = ctypes.c_long
         L.orc_step.argtypes = [cp, dp, ctypes.c_double]; L.orc_step.restype = ctypes.c_int
         L.orc_dt_cfl.argtypes = [cp, dp]; L.orc_dt_cfl.restype = ctypes.c_double
@@ -115,6 +116,11 @@ def make_cfg(shape, length=(1.0, 1.0, 1.0), eos="adiabatic_mhd", gamma=5.0 / 3.0
 
 def num_threads() -> int:
     return int(_lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on (results do not depend on it)."""
+    _lib().orc_set_num_threads(int(n))
 
 
 def state_len(cfg: OrcCfg) -> int:

@@ -1,8 +1,10 @@
 """FP64 reference of the learned subgrid flux-correction closure -- TEST INFRASTRUCTURE
 ONLY (imported by tests/, never by the library or its binding).
 
-The paper names a learned closure as future work only (Sec. "Conclusions"); what is
-fixed here is the construction around the network, which the method dictates:
+The closure is an extension of this project, not part of the paper's method: the paper
+only remarks that a neural surrogate could stand in for an expensive cell-local solve
+such as astrochemistry (Sec. "Discussion and Summary").  What is fixed here is the
+construction around the network, which the method dictates:
 
 * input: the 8 primitive channels of the coarse state at the start of a step
   (rho, v_x, v_y, v_z, p, B_x, B_y, B_z at cell centres; B_cc the mean of the two

@@ -104,6 +104,15 @@ int orc_num_threads(void)
 #endif
 }
 
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 long orc_state_len(const orc_cfg* c)
 {
     long n = (long)c->nx * c->ny * c->nz;

@@ -45,6 +45,9 @@ typedef struct {
 /* Threads the OpenMP loops of the oracle use. */
 int orc_num_threads(void);
 
+/* Threads for the OpenMP loops from now on (n > 0); the arithmetic does not depend on it. */
+void orc_set_num_threads(int n);
+
 /* Number of doubles in the canonical state of cfg. */
 long orc_state_len(const orc_cfg* cfg);
 

@@ -946,3 +946,30 @@ def test_isothermal_hlle_linear_acoustic_wave_matches_von_neumann_factor():
     assert abs(amp - want) <= 1e-6 * eps, (amp, want)
     # the mode really decayed and moved (not a trivial check)
     assert abs(want) < 0.9 * eps and abs(np.angle(want)) > 0.5
+
+
+@pytest.mark.slow
+def test_turbulence_sensitivity_record_reproduces():
+    """The committed record of the oracle's self-separation on decaying turbulence (which
+    sets the GPU's many-step bound) is what its script computes: seed 1, the one-ulp
+    input perturbation, first 32 steps."""
+    import importlib.util
+    path = os.path.join(GOLDEN, "make_turbulence_sensitivity.py")
+    spec = importlib.util.spec_from_file_location("make_turbulence_sensitivity", path)
+    M = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(M)
+    rec = np.loadtxt(os.path.join(GOLDEN, "turbulence_sensitivity.txt"))
+    rec = rec[rec[:, 0] == 1]
+    cfg = oracle.make_cfg((M.N,) * 3, recon="ppm", riemann="hlld", integ="vl2", courant=0.3)
+    st = I.turbulence(M.N, seed=1)
+    nc = M.N ** 3
+    a = st.copy()
+    e = a[4 * nc:5 * nc]
+    alt = np.arange(nc) % 2 == 0
+    a[4 * nc:5 * nc] = np.where(alt, np.nextafter(e, np.inf), np.nextafter(e, -np.inf))
+    base = st.copy()
+    for k in range(1, 33):
+        dt = oracle.dt_cfl(cfg, base)
+        base = oracle.step(cfg, base, dt)
+        a = oracle.step(cfg, a, dt)
+        assert float(f"{M.class_sep(a, base):.3e}") == rec[k - 1, 2], k

@@ -10,7 +10,8 @@
  * (Sec. "Constrained Transport"), the two-register stages of eq. (two_register) or the
  * IMEX2P pair with closed-form drag solves (Secs. "Multifluid Dust", "Time
  * Integration"), and the time step of eq. (cfl).  The interface mirrors the paper's
- * Mesh / Simulation / set_initial_condition! / run! split (Sec. "User Interface"):
+ * Mesh / Simulation / set_initial_condition! / run! split (Sec. "User Interface,
+ * Problem Setup, and Execution Modes"):
  * a context is created once with every choice fixed and validated, the state is set,
  * and steps are taken.
  *
@@ -88,7 +89,9 @@ typedef struct {
 /* Closure and physical parameters (Sec. "Newtonian Magnetohydrodynamics",
  * Sec. "Multifluid Dust").  gamma: adiabatic index (MHD); cs_iso: isothermal sound
  * speed (isothermal hydro); rho_floor, p_floor: floors applied to the primitives of
- * the gas; dust_rho_floor: dust densities below it are read as the floor at rest;
+ * the gas; dust_rho_floor: a step first resets every species whose density is below
+ * it to the floor at rest (a species that stage 1 drives below it is read as the floor
+ * at rest);
  * t_stop: constant stopping time of each of the ndust species; gas_accel: constant
  * acceleration of the gas alone, applied as an unsplit source. */
 typedef struct {
@@ -135,13 +138,19 @@ mhd_status mhd_create(const mhd_grid* grid, const mhd_physics* phys, const mhd_s
 mhd_status mhd_state_len(const mhd_ctx* ctx, size_t* n);
 
 /* Copy a canonical FP64 state in (src on the device if src_is_device, else host
- * memory; host copies complete before return).  Also computes the CFL step of the
+ * memory; host copies complete before return).  The state is the one the method
+ * advances: cell averages of the conserved variables (Sec. "Reconstruction and Riemann
+ * Solvers", eq. (fv_update)) in the i-fastest array layout of Sec. "Mesh, Coordinates,
+ * and Boundary Conditions", then (MHD) the area-averaged normal field on the faces of
+ * Sec. "Constrained Transport".  Also computes the CFL step of the
  * new state on the device.  The FP32-bulk form rounds every field but E to FP32 here
  * (every field for the dust path; the CFL step is that of the FP64 state as given). */
 mhd_status mhd_set_state(mhd_ctx* ctx, const double* src, int src_is_device);
 
-/* Copy the current state out in canonical layout; a copy to host memory completes
- * before return, a copy to device memory is ordered on the stream. */
+/* Copy the current state out in canonical layout (the complete state that continues a
+ * run, as the paper's restart output writes it at working precision, Sec. "Output and
+ * Restart"); a copy to host memory completes before return, a copy to device memory is
+ * ordered on the stream. */
 mhd_status mhd_get_state(mhd_ctx* ctx, double* dst, int dst_is_device);
 
 /* Advance the state by exactly dt (one full step of the configured integrator; the
@@ -173,8 +182,9 @@ mhd_status mhd_dt_cfl(mhd_ctx* ctx, double* dt);
 mhd_status mhd_dt_cfl_noalloc(const mhd_grid* grid, const mhd_physics* phys, const mhd_scheme* scheme,
                               const double* state_device, double* dt_device, void* hip_stream);
 
-/* Volume integrals and extrema of the current state, in FP64 with a fixed-order
- * (deterministic) reduction.  out must hold n >= 12 + ndust doubles:
+/* Volume integrals and extrema of the current state, the history diagnostics of
+ * Sec. "Output and Restart" (total mass, momentum and energy, the maximum |div B| for
+ * MHD), in FP64 with a fixed-order (deterministic) reduction.  out must hold n >= 12 + ndust doubles:
  *   out[0] gas mass, out[1..3] gas momentum, out[4] total energy (0 if isothermal),
  *   out[5..7] volume integral of the face fields (0 without MHD), out[8] max |div B|
  *   over cells, out[9 .. 8+ndust] dust masses, out[9+ndust .. 11+ndust] total momentum
@@ -204,8 +214,9 @@ void mhd_destroy(mhd_ctx* ctx);
 const char* mhd_strerror(mhd_status status);
 
 /* ---------------------------------------------------------------------------------
- * Batched meshblocks.  The paper advances a list of meshblocks with the block index as
- * one more launch dimension (Sec. "Mesh and Data Layout"; Table "MeshBlock").  A batch
+ * Batched meshblocks.  The paper advances all the meshblocks a rank owns in one launch,
+ * with the block index as one more dimension of the launch (Sec. "Mesh, Coordinates,
+ * and Boundary Conditions").  A batch
  * here is a set of nblocks INDEPENDENT self-periodic adiabatic-MHD boxes of any sizes
  * sharing one physics and scheme; every stage kernel is one persistent launch that
  * drains a device work queue of (block, tile, z chunk) items.  The stencil halo of
@@ -264,8 +275,10 @@ mhd_status mhd_batch_tune(mhd_batch* batch, int reps, float* ms_out, int nout);
 void mhd_batch_destroy(mhd_batch* batch);
 
 /* ---------------------------------------------------------------------------------
- * Learned subgrid flux-correction closure of the coarse step.  The paper lists learned
- * closures as future work (Sec. "Conclusions"); the network here sees the 8 primitive
+ * Learned subgrid flux-correction closure of the coarse step.  This is an extension of
+ * this library, not part of the paper's method: the paper only remarks that a neural
+ * surrogate could stand in for an expensive cell-local solve such as astrochemistry
+ * (Sec. "Discussion and Summary").  The network here sees the 8 primitive
  * channels (rho, v, p, B_cc) of the coarse state at the start of a step, normalised as
  * (w - mu) / sd, and returns 18 channels per cell: face-flux corrections of rho, M_x,
  * M_y, M_z, E through the low x, y, z faces (channel 3 f + d, scaled by sF[f]) and
@@ -313,10 +326,15 @@ mhd_status mhd_cnn_accumulate(mhd_cnn* cnn, const double* state_t, const double*
 /* Adam step `step` (>= 1) on grad_scale * gradients. */
 mhd_status mhd_cnn_adam(mhd_cnn* cnn, float lr, float beta1, float beta2, float eps, int step,
                         float grad_scale);
-/* One closure step of a context: corrections from its current state, the plain step by
- * dt, the corrections added (the context's CFL step is refreshed).  The context's grid
- * must be the network's. */
-mhd_status mhd_step_closure(mhd_ctx* ctx, mhd_cnn* cnn, double dt);
+/* One closure step of a context, in place: corrections from its current state (read
+ * where it lives), the plain step by dt, then the corrections added to the stepped
+ * state if that leaves every cell finite with density and pressure at or above the
+ * floors; otherwise the plain step stands (the fallback).  The context's CFL step is
+ * then refreshed.  *applied (if not NULL; reading it synchronises the stream) is 1
+ * when the corrections were applied, 0 for the fallback.  The context must be FP64
+ * adiabatic MHD (else MHD_E_UNSUPPORTED), on the network's grid (cells and spacing) and
+ * on the network's stream (else MHD_E_INVAL). */
+mhd_status mhd_step_closure(mhd_ctx* ctx, mhd_cnn* cnn, double dt, int* applied);
 /* Box filter of a fine canonical state (device) onto the grid r times coarser: cell
  * fields averaged over r^3 cells, face fields over the r^2 fine faces of each coarse
  * face (so the coarse div B is the mean of the fine one).  Asynchronous. */

@@ -114,7 +114,7 @@ def load_library(path: str = LIB_PATH):
     L.mhd_cnn_accumulate.argtypes = [vp, vp, vp, vp, ctypes.c_double, dp]
     L.mhd_cnn_adam.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int,
                                ctypes.c_float]
-    L.mhd_step_closure.argtypes = [vp, vp, ctypes.c_double]
+    L.mhd_step_closure.argtypes = [vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_int)]
     L.mhd_box_filter.argtypes = [ctypes.POINTER(MhdGrid), ctypes.c_int, vp, vp, vp]
     L.mhd_cnn_destroy.argtypes = [vp]
     L.mhd_cnn_destroy.restype = None
@@ -432,9 +432,14 @@ def mhd_cnn_adam(cnn: int, lr: float, beta1: float, beta2: float, eps: float, st
                                        int(step), float(grad_scale)), "mhd_cnn_adam")
 
 
-def mhd_step_closure(ctx: int, cnn: int, dt: float):
-    _check(load_library().mhd_step_closure(ctypes.c_void_p(ctx), ctypes.c_void_p(cnn), ctypes.c_double(dt)),
+def mhd_step_closure(ctx: int, cnn: int, dt: float, report: bool = False):
+    """One closure step; with report, returns whether the corrections were applied (1)
+    or the plain step was kept (0) (reading it synchronises)."""
+    flag = ctypes.c_int(-1)
+    _check(load_library().mhd_step_closure(ctypes.c_void_p(ctx), ctypes.c_void_p(cnn), ctypes.c_double(dt),
+                                           ctypes.byref(flag) if report else None),
            "mhd_step_closure")
+    return flag.value if report else None
 
 
 def mhd_box_filter(fine_grid: MhdGrid, r: int, fine_ptr: int, coarse_ptr: int, stream_ptr: int):
@@ -685,9 +690,10 @@ class Closure:
         self.step_count += 1
         mhd_cnn_adam(self.ctx, lr, beta1, beta2, eps, self.step_count, grad_scale)
 
-    def step(self, sim, dt):
-        """One closure step of a Sim on the same grid."""
-        mhd_step_closure(sim.ctx, self.ctx, dt)
+    def step(self, sim, dt, report: bool = False):
+        """One closure step of a Sim on the same grid and stream; with report, returns 1
+        if the corrections were applied, 0 if the plain step was kept."""
+        return mhd_step_closure(sim.ctx, self.ctx, dt, report)
 
     def close(self):
         if getattr(self, "ctx", 0):

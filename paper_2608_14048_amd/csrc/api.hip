@@ -28,8 +28,8 @@ enum TimerSlot {
     T_NSLOT
 };
 static const char* const kSlotNames[T_NSLOT] = {
-    "mhd_flux_predictor", "mhd_flux_corrector", "mhd_ct_update_predictor",
-    "mhd_ct_update_corrector", "cfl", "dust_fluid_pass_stage1", "dust_fluid_pass_stage2",
+    "mhd_flux_update_predictor", "mhd_flux_update_corrector", "mhd_ct_predictor",
+    "mhd_ct_corrector", "cfl", "dust_fluid_pass_stage1", "dust_fluid_pass_stage2",
     "dust_drag_stage1", "dust_drag_cfl_stage2"};
 
 struct EventTimer {
@@ -52,7 +52,7 @@ struct mhd_ctx {
     bool fp32;      // FP32 registers: FP32-bulk MHD form, or FP32 dust (FP64 drag solve)
     // workspace views
     void* reg[3];   // state registers (MHD rotates all three; see reg_view for the layout)
-    void* F;        // MHD face fluxes, 3 direction blocks (the path's real type)
+    void* F;        // MHD: the 9 face fields of the edge EMFs (the path's real type)
     void* Rc;       // cell-centred E = -v x B (MHD)
     FusedGrid fg;   // tiling of the MHD stage kernels
     DustGrid dg;    // tiling of the dust fluid passes
@@ -108,14 +108,18 @@ struct Layout {
     size_t reg, nreg, F, Rc, partial, scalars, total;
 };
 
-// z planes per workgroup of the MHD kernels: about 3072 workgroups on large grids, four
-// full rounds of the 768 that the FP64 PPM flux kernel keeps resident (three per CU).
+Geo make_geo(const mhd_grid* grid);
+
+// z planes per workgroup of the MHD kernels: about 3072 flux/update workgroups on large
+// grids, four full rounds of the 768 that the FP64 PPM kernel keeps resident (three per
+// CU); each chunk primes its z pipeline once, so chunks stay at least 8 planes long.
 int choose_kz(const mhd_grid* g)
 {
-    const long long tiles = (long long)((g->nx + 63) / 64) * ((g->ny + 3) / 4);
+    const long long per_plane = (long long)flux_tile_cells();
+    const long long tiles = ((long long)g->nx * g->ny + per_plane - 1) / per_plane;
     const long long want = (3072 + tiles - 1) / tiles;
     int kz = (int)((g->nz + want - 1) / want);
-    if (kz < 4) kz = 4;
+    if (kz < 8) kz = 8;
     if (kz > g->nz) kz = g->nz;
     return kz;
 }
@@ -208,7 +212,7 @@ Layout layout(const mhd_grid* g, const mhd_physics* p, const mhd_scheme* sc)
     // for the FP32 forms the flux area also stages a canonical FP64 state (nv fields);
     // the FP64 dust path keeps no arrays besides its two registers
     if (is_mhd)
-        L.F = align256(rfield * 21 > field * 8 ? rfield * 21 : field * 8);
+        L.F = align256(rfield * 9 > field * 8 ? rfield * 9 : field * 8);
     else
         L.F = fp32 ? align256(field * nv) : 0;
     L.Rc = is_mhd ? align256(rfield * 3) : 0;
@@ -272,16 +276,17 @@ mhd_status cfl_of(mhd_ctx* c, const double* U)
     return dev(launch_cfl_dust(c->geo, c->dp, U, c->partial, c->scalars, c->cfl_scale, c->stream));
 }
 
-// One stage: fluxes of `in`, then out = g0 in + g1 base + bdt L(in) (and, if last,
-// the CFL step of out into scalars[0]).
+// One stage: out = g0 in + g1 base + bdt L(in): the cell fields with the fluxes of
+// `in`, then the face fields from the edge EMFs (and, if last, the CFL step of out into
+// scalars[0]).
 mhd_status mhd_stage(mhd_ctx* c, int recon, void* in, void* base, void* out, StageCoef co,
                      bool corrector, bool last)
 {
     hipError_t e;
     {
         Tick t(c, corrector ? T_MHD_FLUX_CORR : T_MHD_FLUX_PRED);
-        e = launch_mhd_flux3(c->geo, c->mp, c->fg, c->fp32, recon, c->scheme.riemann, in, c->F, c->Rc,
-                             c->stream);
+        e = launch_mhd_flux3(c->geo, c->mp, c->fg, c->fp32, recon, c->scheme.riemann, in, base, out, c->F,
+                             c->Rc, co, c->stream);
     }
     if (e == hipSuccess) {
         Tick t(c, corrector ? T_MHD_CT_CORR : T_MHD_CT_PRED);
@@ -350,6 +355,28 @@ mhd_status step_dust(mhd_ctx* c, double dt)
 }
 
 }  // namespace
+
+namespace mhd {
+
+CtxView ctx_view(mhd_ctx* c)
+{
+    CtxView v;
+    v.geo = c->geo;
+    v.mp = c->mp;
+    v.stream = c->stream;
+    v.state = c->is_mhd && !c->fp32 ? (double*)c->reg[c->cur] : nullptr;
+    return v;
+}
+
+hipError_t ctx_refresh_cfl(mhd_ctx* c)
+{
+    hipError_t e;
+    const double* U = canonical_view(c, &e);
+    if (e != hipSuccess) return e;
+    return cfl_of(c, U) == MHD_OK ? hipSuccess : hipErrorLaunchFailure;
+}
+
+}  // namespace mhd
 
 extern "C" {
 

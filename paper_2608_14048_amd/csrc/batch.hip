@@ -1,7 +1,8 @@
 // batch.hip -- many self-periodic meshblocks of uneven sizes advanced together.
 //
-// The paper runs a list of meshblocks with the block index as one more launch
-// dimension (Sec. "Mesh and Data Layout"); here the blocks are independent periodic
+// The paper advances the meshblocks a rank owns in one launch, with the block index as
+// one more launch dimension (Sec. "Mesh, Coordinates, and Boundary Conditions"); here
+// the blocks are independent periodic
 // boxes of any sizes, and each stage kernel is one persistent launch per tile shape in
 // use (one launch for all blocks when they share a shape, three at most): a queue of
 // (block, tile, z chunk) work items, longest first, that the workgroups of the launch
@@ -73,27 +74,6 @@ __device__ __forceinline__ int next_item(unsigned long long* ctr, unsigned long 
     return it;
 }
 
-template <int RECON, int RS, class R, int SHAPE>
-__global__ __launch_bounds__(kFluxThreads) void k_flux3_batch(const BlockDesc* __restrict__ blk,
-                                                             const WorkItem* __restrict__ items, int nitems,
-                                                             unsigned long long* ctr, unsigned long long base,
-                                                             MhdParams P, char* reg, int reg_bpc, R* F, R* Rc)
-{
-    constexpr int TX = SHAPE == 0 ? 64 : (SHAPE == 1 ? 32 : 16);
-    using Tile = FluxTile<RECON, RS, R, TX, kFluxThreads / TX>;
-    __shared__ typename Tile::Lds lds;
-    __shared__ int slot;
-    for (;;) {
-        const int it = next_item(ctr, base, &slot);
-        if (it < 0 || it >= nitems) break;
-        const WorkItem w = items[it];
-        const BlockDesc b = blk[w.block];
-        const RegView<R> U = reg_view<R>(reg + b.off * (unsigned long long)reg_bpc, b.g.n);
-        Tile::run(b.g, P, U, F + b.off * 21ULL, Rc + b.off * 3ULL, w.x0, w.y0, w.k0, w.k1, lds);
-        __syncthreads();  // the next item reuses the LDS
-    }
-}
-
 struct BatchCt {
     char* in;
     char* base;
@@ -103,6 +83,30 @@ struct BatchCt {
     const double* dt;     // per block
     double* partial;      // per item (CFL)
 };
+
+template <int RECON, int RS, bool IN, class R, int SHAPE>
+__global__ __launch_bounds__(kFluxThreads) void k_flux3_batch(const BlockDesc* __restrict__ blk,
+                                                             const WorkItem* __restrict__ items, int nitems,
+                                                             unsigned long long* ctr, unsigned long long base,
+                                                             MhdParams P, BatchCt a, R* F, R* Rc)
+{
+    constexpr int TX = SHAPE == 0 ? 64 : (SHAPE == 1 ? 32 : 16);
+    using Tile = FluxTile<RECON, RS, IN, R, TX, kFluxThreads / TX>;
+    __shared__ typename Tile::Lds lds;
+    __shared__ int slot;
+    for (;;) {
+        const int it = next_item(ctr, base, &slot);
+        if (it < 0 || it >= nitems) break;
+        const WorkItem w = items[it];
+        const BlockDesc b = blk[w.block];
+        const unsigned long long ob = b.off * (unsigned long long)a.reg_bpc;
+        const StageArgs<R> s{reg_view<R>(a.in + ob, b.g.n), reg_view<R>(a.base + ob, b.g.n),
+                             reg_view<R>(a.out + ob, b.g.n), F + b.off * (unsigned long long)NFACE,
+                             Rc + b.off * 3ULL, StageCoef{a.g0, a.g1, a.beta * a.dt[w.block]}};
+        Tile::run(b.g, P, s, w.x0, w.y0, w.k0, w.k1, lds);
+        __syncthreads();  // the next item reuses the LDS
+    }
+}
 
 // items: this launch's items, which start at item id `first` of the whole list (the
 // CFL partial of item id q goes to partial[q]).
@@ -123,7 +127,7 @@ __global__ __launch_bounds__(kCtThreads) void k_ct_batch(const BlockDesc* __rest
         const WorkItem w = items[it];
         const BlockDesc b = blk[w.block];
         const unsigned long long ob = b.off * (unsigned long long)a.reg_bpc;
-        CtArgs<R> c{reg_view<R>(a.in + ob, b.g.n), reg_view<R>(a.base + ob, b.g.n), F + b.off * 21ULL,
+        CtArgs<R> c{reg_view<R>(a.in + ob, b.g.n), reg_view<R>(a.base + ob, b.g.n), F + b.off * (unsigned long long)NFACE,
                     Rc + b.off * 3ULL, reg_view<R>(a.out + ob, b.g.n), nullptr,
                     StageCoef{a.g0, a.g1, a.beta * a.dt[w.block]}};
         double vmin = Tile::run(b.g, P, c, w.x0, w.y0, w.k0, w.k1, lds);
@@ -274,7 +278,7 @@ BLayout blayout(int nb, const mhd_grid* grids, const mhd_scheme* s)
     L.cap_f = (int)cf;
     L.cap_c = (int)cc;
     L.reg = a256((size_t)o * register_bytes(1, fp32));
-    L.F = a256(std::max((size_t)o * 21 * rsz, (size_t)o * 8 * sizeof(double)));
+    L.F = a256(std::max((size_t)o * NFACE * rsz, (size_t)o * 8 * sizeof(double)));
     L.Rc = a256((size_t)o * 3 * rsz);
     L.partial = a256((size_t)std::max(cc, maxblk) * sizeof(double));
     L.dt = a256((size_t)nb * sizeof(double));
@@ -361,36 +365,44 @@ mhd_status build_all(mhd_batch* c) { return build_items(c, std::vector<char>(c->
 
 int persistent_grid(const mhd_batch* c, int nitems) { return std::max(1, std::min(nitems, 4 * c->cus)); }
 
-template <int RECON, int RS, class R, int SH>
-void flux_launch(mhd_batch* c, char* in)
+template <int RECON, int RS, bool IN, class R, int SH>
+void flux_launch(mhd_batch* c, const BatchCt& a)
 {
     const int m = c->fbeg[SH + 1] - c->fbeg[SH];
     if (m == 0) return;
     const int grid = persistent_grid(c, m);
-    hipLaunchKernelGGL((k_flux3_batch<RECON, RS, R, SH>), dim3(grid), dim3(kFluxThreads), 0, c->stream, c->d_blk,
-                       c->d_fitems + c->fbeg[SH], m, c->ctr, c->base[0], c->mp, in, c->reg_bpc, (R*)c->F, (R*)c->Rc);
+    hipLaunchKernelGGL((k_flux3_batch<RECON, RS, IN, R, SH>), dim3(grid), dim3(kFluxThreads), 0, c->stream,
+                       c->d_blk, c->d_fitems + c->fbeg[SH], m, c->ctr, c->base[0], c->mp, a, (R*)c->F,
+                       (R*)c->Rc);
     c->base[0] += (unsigned long long)m + grid;
 }
 
-template <int RECON, int RS, class R>
-void flux_shapes(mhd_batch* c, char* in)
+template <int RECON, int RS, bool IN, class R>
+void flux_shapes(mhd_batch* c, const BatchCt& a)
 {
-    flux_launch<RECON, RS, R, 0>(c, in);
-    flux_launch<RECON, RS, R, 1>(c, in);
-    flux_launch<RECON, RS, R, 2>(c, in);
+    flux_launch<RECON, RS, IN, R, 0>(c, a);
+    flux_launch<RECON, RS, IN, R, 1>(c, a);
+    flux_launch<RECON, RS, IN, R, 2>(c, a);
+}
+
+template <int RECON, int RS, class R>
+void flux_in(mhd_batch* c, const BatchCt& a, bool use_in)
+{
+    if (use_in) flux_shapes<RECON, RS, true, R>(c, a);
+    else flux_shapes<RECON, RS, false, R>(c, a);
 }
 
 template <class R>
-void flux_any(mhd_batch* c, int recon, char* in)
+void flux_any(mhd_batch* c, int recon, const BatchCt& a, bool use_in)
 {
     if (c->scheme.riemann == MHD_RS_HLLD) {
-        if (recon == 0) flux_shapes<0, 1, R>(c, in);
-        else if (recon == 1) flux_shapes<1, 1, R>(c, in);
-        else flux_shapes<2, 1, R>(c, in);
+        if (recon == 0) flux_in<0, 1, R>(c, a, use_in);
+        else if (recon == 1) flux_in<1, 1, R>(c, a, use_in);
+        else flux_in<2, 1, R>(c, a, use_in);
     } else {
-        if (recon == 0) flux_shapes<0, 0, R>(c, in);
-        else if (recon == 1) flux_shapes<1, 0, R>(c, in);
-        else flux_shapes<2, 0, R>(c, in);
+        if (recon == 0) flux_in<0, 0, R>(c, a, use_in);
+        else if (recon == 1) flux_in<1, 0, R>(c, a, use_in);
+        else flux_in<2, 0, R>(c, a, use_in);
     }
 }
 
@@ -426,17 +438,19 @@ void ct_any(mhd_batch* c, const BatchCt& a, bool cfl, bool use_in)
     }
 }
 
-// One stage over every block: fluxes of `in`, then out = g0 in + g1 base + beta dt L
-// (and, if last, the CFL step of out into dt[]).
+// One stage over every block: out = g0 in + g1 base + beta dt L: the cell fields with
+// the fluxes of `in`, then the face fields from the edge EMFs (and, if last, the CFL
+// step of out into dt[]).
 mhd_status bstage(mhd_batch* c, int recon, char* in, char* base, char* out, double g0, double g1,
                   double beta, bool last)
 {
-    if (c->fp32) flux_any<float>(c, recon, in);
-    else flux_any<double>(c, recon, in);
+    BatchCt a{in, base, out, c->reg_bpc, g0, g1, beta, c->dt, c->partial};
+    const bool flux_in_reg = g0 != 0.0 || c->mp.gacc[0] != 0.0 || c->mp.gacc[1] != 0.0 || c->mp.gacc[2] != 0.0;
+    if (c->fp32) flux_any<float>(c, recon, a, flux_in_reg);
+    else flux_any<double>(c, recon, a, flux_in_reg);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return MHD_E_DEVICE;
-    BatchCt a{in, base, out, c->reg_bpc, g0, g1, beta, c->dt, c->partial};
-    const bool use_in = g0 != 0.0 || c->mp.gacc[0] != 0.0 || c->mp.gacc[1] != 0.0 || c->mp.gacc[2] != 0.0;
+    const bool use_in = g0 != 0.0;
     if (c->fp32) ct_any<float>(c, a, last, use_in);
     else ct_any<double>(c, a, last, use_in);
     e = hipGetLastError();

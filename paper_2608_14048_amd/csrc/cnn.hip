@@ -1,7 +1,9 @@
 // cnn.hip -- the learned subgrid flux-correction closure of the coarse MHD step.
 //
-// The paper names learned closures as future work (Sec. "Conclusions"); the
-// construction around the network follows the method: the network sees the 8
+// An extension of this library, not part of the paper's method (the paper only
+// remarks, Sec. "Discussion and Summary", that a neural surrogate could replace an
+// expensive cell-local solve such as astrochemistry).  The construction around the
+// network follows the method: the network sees the 8
 // primitive channels of the coarse state at the start of a step and returns 15 face-
 // flux corrections (rho, M_x, M_y, M_z, E through the low x, y and z face of each cell)
 // and 3 edge-EMF corrections (E_x on edge (i, j-1/2, k-1/2), E_y on (i-1/2, j, k-1/2),
@@ -32,7 +34,7 @@
 #include <vector>
 
 #include "../../include/mhd950.h"
-#include "common.hpp"
+#include "launch.hpp"
 
 using namespace mhd;
 
@@ -351,34 +353,94 @@ __global__ __launch_bounds__(kThreads) void k_bgrad(Geo g, const bf16_t* __restr
     }
 }
 
-// The closure in flux and constrained-transport form on a canonical FP64 state, in place
-// (each thread writes only its own cell and faces; O is read-only).
-__global__ __launch_bounds__(kThreads) void k_closure_apply(Geo g, const float* __restrict__ O, const float* __restrict__ sF,
-                                                            float sE, double dt, double* __restrict__ U)
+// The closure in flux and constrained-transport form: the corrected value of field q of
+// cell c (q < 5: the cell field minus dt times the divergence of the face-flux
+// corrections; q >= 5: the face field minus dt times the curl of the edge-EMF
+// corrections).  Shared by the check and the update so that both see the same bits.
+struct CorrIdx {
+    unsigned int c, cp[3];  // the cell and its +x, +y, +z neighbours
+};
+__device__ __forceinline__ CorrIdx corr_idx(const Geo& g, unsigned int c)
 {
-    const unsigned int c = blockIdx.x * kThreads + threadIdx.x;
-    if (c >= (unsigned int)g.n) return;
-    const unsigned int n = (unsigned int)g.n;
     const int x = (int)(c % (unsigned int)g.nx), y = (int)((c / (unsigned int)g.nx) % (unsigned int)g.ny);
     const int z = (int)(c / ((unsigned int)g.nx * (unsigned int)g.ny));
-    const unsigned int cp[3] = {tap_voxel(g, x, y, z, 14), tap_voxel(g, x, y, z, 16), tap_voxel(g, x, y, z, 22)};
-#pragma unroll
-    for (int f = 0; f < 5; ++f) {
+    return CorrIdx{c, {tap_voxel(g, x, y, z, 14), tap_voxel(g, x, y, z, 16), tap_voxel(g, x, y, z, 22)}};
+}
+__device__ __forceinline__ double corrected(const Geo& g, const float* __restrict__ O, const float* __restrict__ sF,
+                                            float sE, double dt, const double* __restrict__ U, const CorrIdx& k, int q)
+{
+    const unsigned int n = (unsigned int)g.n, c = k.c;
+    if (q < 5) {
         double div = 0.0;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            const float* o = O + (size_t)(3 * f + d) * n;
-            div += (double)sF[f] * ((double)o[cp[d]] - (double)o[c]) * g.inv_dx[d];
+            const float* o = O + (size_t)(3 * q + d) * n;
+            div += (double)sF[q] * ((double)o[k.cp[d]] - (double)o[c]) * g.inv_dx[d];
         }
-        U[(size_t)f * n + c] -= dt * div;
+        return U[(size_t)q * n + c] - dt * div;
     }
     const float* Ex = O + (size_t)15 * n;
     const float* Ey = O + (size_t)16 * n;
     const float* Ez = O + (size_t)17 * n;
-    auto dE = [&](const float* e, int d) { return (double)sE * ((double)e[cp[d]] - (double)e[c]) * g.inv_dx[d]; };
-    U[(size_t)5 * n + c] -= dt * (dE(Ez, 1) - dE(Ey, 2));
-    U[(size_t)6 * n + c] -= dt * (dE(Ex, 2) - dE(Ez, 0));
-    U[(size_t)7 * n + c] -= dt * (dE(Ey, 0) - dE(Ex, 1));
+    auto dE = [&](const float* e, int d) { return (double)sE * ((double)e[k.cp[d]] - (double)e[c]) * g.inv_dx[d]; };
+    const double curl = q == 5 ? dE(Ez, 1) - dE(Ey, 2) : (q == 6 ? dE(Ex, 2) - dE(Ez, 0) : dE(Ey, 0) - dE(Ex, 1));
+    return U[(size_t)q * n + c] - dt * curl;
+}
+
+// The closure on a canonical FP64 state, in place (each thread writes only its own cell
+// and faces; O is read-only).  With ok non-null nothing is written unless *ok > 0.
+__global__ __launch_bounds__(kThreads) void k_closure_apply(Geo g, const float* __restrict__ O, const float* __restrict__ sF,
+                                                            float sE, double dt, double* __restrict__ U,
+                                                            const double* __restrict__ ok)
+{
+    const unsigned int c = blockIdx.x * kThreads + threadIdx.x;
+    if (c >= (unsigned int)g.n) return;
+    if (ok && !(ok[0] > 0.0)) return;
+    const CorrIdx k = corr_idx(g, c);
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = corrected(g, O, sF, sE, dt, U, k, q);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) U[(size_t)q * g.n + c] = v[q];
+}
+
+// Whether the closure would leave cell c valid: every corrected value finite, the density
+// and the pressure (from the corrected total energy, momenta and the mean of the
+// corrected bounding faces) at or above the floors.  One partial per workgroup: +inf if
+// all its cells are valid, else -1.
+__global__ __launch_bounds__(kThreads) void k_closure_check(Geo g, const float* __restrict__ O, const float* __restrict__ sF,
+                                                            float sE, double dt, const double* __restrict__ U,
+                                                            double gamma, double rho_floor, double p_floor,
+                                                            double* __restrict__ partial)
+{
+    const unsigned int c = blockIdx.x * kThreads + threadIdx.x;
+    bool good = true;
+    if (c < (unsigned int)g.n) {
+        const CorrIdx k = corr_idx(g, c);
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = corrected(g, O, sF, sE, dt, U, k, q);
+        const double hi[3] = {corrected(g, O, sF, sE, dt, U, corr_idx(g, k.cp[0]), 5),
+                              corrected(g, O, sF, sE, dt, U, corr_idx(g, k.cp[1]), 6),
+                              corrected(g, O, sF, sE, dt, U, corr_idx(g, k.cp[2]), 7)};
+        double bb = 0.0, mm = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double b = 0.5 * (v[5 + d] + hi[d]);
+            bb += b * b;
+            mm += v[1 + d] * v[1 + d];
+        }
+        const double p = (gamma - 1.0) * (v[4] - 0.5 * mm / v[0] - 0.5 * bb);
+        for (int q = 0; q < 8; ++q) good = good && isfinite(v[q]);
+        good = good && isfinite(hi[0]) && isfinite(hi[1]) && isfinite(hi[2]);
+        good = good && v[0] >= rho_floor && p >= p_floor && isfinite(p);
+    }
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    if (!good) atomicOr(&bad, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = bad ? -1.0 : INFINITY;
 }
 
 // rw[f][c] = 2 w_f (P - T) / n and the loss partial sum_f w_f (P - T)^2 / n per block.
@@ -517,7 +579,6 @@ struct mhd_cnn {
     bf16_t *D0, *D1;         // backward gradients [n][32]
     float* RW;               // weighted residual [8][n]
     double* Pred;            // corrected prediction [8][n]
-    double* Tmp;             // a state copy for the closure step [8][n]
     double* partial;
     float* scal;             // mu[8], sd[8], sF[5], w8[8]
     float sE;
@@ -529,7 +590,7 @@ namespace {
 size_t ca(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct CLayout {
-    size_t params, wf[kLayers], wb[kLayers], a[kLayers], o, d, rw, pred, tmp, partial, scal, total;
+    size_t params, wf[kLayers], wb[kLayers], a[kLayers], o, d, rw, pred, partial, scal, total;
 };
 
 CLayout clayout(const mhd_grid* g)
@@ -546,10 +607,9 @@ CLayout clayout(const mhd_grid* g)
     L.d = ca(n * kNPad * sizeof(bf16_t));
     L.rw = ca(n * 8 * sizeof(float));
     L.pred = ca(n * 8 * sizeof(double));
-    L.tmp = ca(n * 8 * sizeof(double));
-    L.partial = ca(((n + kThreads - 1) / kThreads) * sizeof(double));
+    L.partial = ca(((n + kThreads - 1) / kThreads + 1) * sizeof(double));  // + the closure's flag
     L.scal = ca(64 * sizeof(float));
-    L.total = 4 * L.params + L.o + 2 * L.d + L.rw + L.pred + L.tmp + L.partial + L.scal;
+    L.total = 4 * L.params + L.o + 2 * L.d + L.rw + L.pred + L.partial + L.scal;
     for (int l = 0; l < kLayers; ++l) L.total += L.wf[l] + L.wb[l] + L.a[l];
     return L;
 }
@@ -617,11 +677,22 @@ hipError_t forward(mhd_cnn* c, const double* U)
     return hipGetLastError();
 }
 
-hipError_t apply(mhd_cnn* c, double dt, double* U)
+hipError_t apply(mhd_cnn* c, double dt, double* U, const double* ok = nullptr)
 {
     hipLaunchKernelGGL(k_closure_apply, dim3(c->nblk), dim3(kThreads), 0, c->stream, c->g, c->O, c->scal + 16, c->sE,
-                       dt, U);
+                       dt, U, ok);
     return hipGetLastError();
+}
+
+// flag[0] = +inf if the closure leaves every cell of U valid, else -1 (partials in
+// c->partial, the flag just after them).
+hipError_t check(mhd_cnn* c, double dt, const double* U, const MhdParams& mp, double* flag)
+{
+    hipLaunchKernelGGL(k_closure_check, dim3(c->nblk), dim3(kThreads), 0, c->stream, c->g, c->O, c->scal + 16, c->sE,
+                       dt, U, c->gamma, mp.rho_floor, mp.p_floor, c->partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_min_final(c->partial, c->nblk, 1.0, flag, c->stream);
 }
 
 }  // namespace
@@ -682,7 +753,6 @@ mhd_status mhd_cnn_create(const mhd_grid* grid, const mhd_physics* phys, void* w
     c->D1 = (bf16_t*)p; p += L.d;
     c->RW = (float*)p; p += L.rw;
     c->Pred = (double*)p; p += L.pred;
-    c->Tmp = (double*)p; p += L.tmp;
     c->partial = (double*)p; p += L.partial;
     c->scal = (float*)p;
     c->sE = 1.0f;
@@ -839,22 +909,36 @@ mhd_status mhd_cnn_adam(mhd_cnn* c, float lr, float beta1, float beta2, float ep
     return cdev(e);
 }
 
-mhd_status mhd_step_closure(mhd_ctx* ctx, mhd_cnn* c, double dt)
+mhd_status mhd_step_closure(mhd_ctx* ctx, mhd_cnn* c, double dt, int* applied)
 {
     if (!ctx || !c || !(dt > 0.0) || !std::isfinite(dt)) return MHD_E_INVAL;
-    size_t len = 0;
-    mhd_status st = mhd_state_len(ctx, &len);
-    if (st != MHD_OK) return st;
-    if (len != (size_t)c->g.n * 8) return MHD_E_INVAL;
-    // corrections from the state at the start of the step, then the plain step, then the
-    // closure on the stepped state (which also refreshes its time step)
-    st = mhd_get_state(ctx, c->Tmp, 1);
-    if (st == MHD_OK) st = cdev(forward(c, c->Tmp));
+    CtxView v = ctx_view(ctx);
+    if (!v.state) return MHD_E_UNSUPPORTED;  // FP64 adiabatic MHD contexts
+    // the same grid (cells and spacing) and the same stream: the network's kernels and
+    // the context's run in one order without events between them
+    if (v.geo.nx != c->g.nx || v.geo.ny != c->g.ny || v.geo.nz != c->g.nz) return MHD_E_INVAL;
+    for (int a = 0; a < 3; ++a)
+        if (v.geo.dx[a] != c->g.dx[a]) return MHD_E_INVAL;
+    if (v.stream != c->stream) return MHD_E_INVAL;
+    double* flag = c->partial + c->nblk;
+    // corrections from the state at the start of the step, read where it lives
+    mhd_status st = cdev(forward(c, v.state));
+    // the plain step, then the closure in place on the stepped state if it leaves every
+    // cell finite and above the floors (else the plain step stands), and the time step
+    // of the result
     if (st == MHD_OK) st = mhd_step(ctx, dt);
-    if (st == MHD_OK) st = mhd_get_state(ctx, c->Tmp, 1);
-    if (st == MHD_OK) st = cdev(apply(c, dt, c->Tmp));
-    if (st == MHD_OK) st = mhd_set_state(ctx, c->Tmp, 1);
-    return st;
+    if (st != MHD_OK) return st;
+    v = ctx_view(ctx);
+    hipError_t e = check(c, dt, v.state, v.mp, flag);
+    if (e == hipSuccess) e = apply(c, dt, v.state, flag);
+    if (e == hipSuccess) e = ctx_refresh_cfl(ctx);
+    if (e == hipSuccess && applied) {
+        double h = 0.0;
+        e = hipMemcpyAsync(&h, flag, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        *applied = h > 0.0 ? 1 : 0;
+    }
+    return cdev(e);
 }
 
 mhd_status mhd_box_filter(const mhd_grid* fine, int r, const double* fine_state, double* coarse_state, void* hip_stream)

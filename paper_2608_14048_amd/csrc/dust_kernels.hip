@@ -337,6 +337,13 @@ __global__ __launch_bounds__(DTX* DTY) void k_fluid_pass(Geo g, DustParams p, Pa
             }
         }
         if (live) {
+            // the step's input u passes the dust floor reset (a species below its floor
+            // becomes the floor at rest) where it enters the combination, in both stages
+            R* uin = STAGE == 1 ? own : ub;
+            if (!gas && uin[0] < dust_floor) {
+                uin[0] = dust_floor;
+                uin[1] = uin[2] = uin[3] = R(0);
+            }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 R L = -acc[v];
@@ -431,16 +438,16 @@ __global__ __launch_bounds__(kBlock) void k_drag(Geo g, DustParams p, DragCoef q
     double r = INFINITY;
     if (cl < n) {
         const unsigned int c = (unsigned int)cl;
-        double rho[ND + 1], r1[ND + 1], iv1[ND + 1], ivn[ND + 1];
+        double rho[ND + 1], r1[ND + 1], ivn[ND + 1], ivg1 = 0.0;
 #pragma unroll
         for (int s = 0; s <= ND; ++s) rho[s] = (double)ld(X + 4LL * s * n, c);
         if constexpr (STAGE == 2) {
 #pragma unroll
             for (int s = 0; s <= ND; ++s) {
                 r1[s] = (double)ld(U1 + 4LL * s * n, c);
-                iv1[s] = inv_density(p, s, r1[s]);
                 ivn[s] = inv_density(p, s, rho[s]);
             }
+            ivg1 = inv_density(p, 0, r1[0]);
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -448,13 +455,14 @@ __global__ __launch_bounds__(kBlock) void k_drag(Geo g, DustParams p, DragCoef q
 #pragma unroll
             for (int s = 0; s <= ND; ++s) mom[s] = (double)ld(X + (4LL * s + 1 + a) * n, c);
             if constexpr (STAGE == 2) {
-                // + (1 - lam - delta) dt G(U1): drag rates of the stage-1 state
-                const double vg = (double)ld(U1 + (1LL + a) * n, c) * iv1[0];
+                // + (1 - lam - delta) dt G(U1): drag rates of the stage-1 state in their
+                // momentum form (rho_k v_g - p_k)/t_k, the map the stage-1 solve inverted
+                const double vg = (double)ld(U1 + (1LL + a) * n, c) * ivg1;
                 double gsum = 0.0;
 #pragma unroll
                 for (int s = 1; s <= ND; ++s) {
-                    const double vk = (double)ld(U1 + (4LL * s + 1 + a) * n, c) * iv1[s];
-                    const double fk = r1[s] * (vg - vk) * q.its[s - 1];
+                    const double pk = (double)ld(U1 + (4LL * s + 1 + a) * n, c);
+                    const double fk = (r1[s] * vg - pk) * q.its[s - 1];
                     mom[s] = mom[s] + q.cg * fk;
                     gsum -= fk;
                 }

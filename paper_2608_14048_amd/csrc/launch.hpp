@@ -5,6 +5,8 @@
 
 #include "common.hpp"
 
+struct mhd_ctx;
+
 namespace mhd {
 
 struct MhdParams {
@@ -21,12 +23,13 @@ struct DustParams {
 
 // ---- adiabatic MHD (z-marching tile kernels) ----
 struct FusedGrid {
-    int kz;                       // z planes per workgroup
-    unsigned int ntx, nty, ntz;   // tiles along x, y, z
-    unsigned int nblk;            // workgroups of the flux kernel
-    unsigned int nty2, nblk2;     // tiles along y and workgroups of the CT/update kernel
+    int kz;                       // z planes per workgroup (both kernels)
+    unsigned int ntx, nty, ntz;   // tiles of the flux/update kernel along x, y, z
+    unsigned int nblk;            // workgroups of the flux/update kernel
+    unsigned int ctx, cty4, cty8; // tiles of the CT kernel along x, and along y for 4 / 8 rows
 };
 FusedGrid fused_grid(const Geo& g, int kz);
+int flux_tile_cells();  // cells per z plane of a flux/update tile
 
 // A state register of the MHD path by role.  FP64 form (R = double): the 8 canonical
 // fields rho, M1..3, E, b1..3.  FP32-bulk form (R = float): E (double) first, then
@@ -62,12 +65,15 @@ inline size_t register_bytes(long long n, bool fp32)
     return fp32 ? (size_t)n * (sizeof(double) + 7 * sizeof(float)) : (size_t)n * 8 * sizeof(double);
 }
 
-// U: the stage-input register.  F: 7 fields per direction, dir-major (mass, Mx, My, Mz,
-// energy, E_t1, E_t2); Rc: 3 fields of the cell E = -v x B (both in the path's real).
-hipError_t launch_mhd_flux3(const Geo& g, const MhdParams& p, const FusedGrid& fg, bool fp32,
-                            int recon, int riemann, void* U, void* F, void* Rc, hipStream_t s);
-// out = g0 in + g1 base + bdt L; out must not alias in or base.  With dt_out the CFL
-// step of out (times cfl_scale) is reduced into dt_out via one partial per workgroup.
+// Fluxes of the stage input `in` and the cell fields of out = g0 in + g1 base + bdt L
+// (out must not alias in or base).  F: the 9 face fields the edge EMFs need (per
+// direction the mass flux and the two face values of E, see FaceField); Rc: 3 fields of
+// the cell E = -v x B (both in the path's real).
+hipError_t launch_mhd_flux3(const Geo& g, const MhdParams& p, const FusedGrid& fg, bool fp32, int recon,
+                            int riemann, void* in, void* base, void* out, void* F, void* Rc, StageCoef coef,
+                            hipStream_t s);
+// The face fields of out = g0 in + g1 base + bdt L from the edge EMFs.  With dt_out the
+// CFL step of out (times cfl_scale) is reduced into dt_out via one partial per workgroup.
 hipError_t launch_mhd_ct_update(const Geo& g, const MhdParams& p, const FusedGrid& fg, bool fp32,
                                 void* in, void* base, const void* F, const void* Rc, void* out,
                                 StageCoef coef, double* partial, double* dt_out, double cfl_scale,
@@ -114,5 +120,16 @@ hipError_t launch_dust_pack(long long m, const double* canon, void* reg, hipStre
 hipError_t launch_dust_unpack(long long m, const void* reg, double* canon, hipStream_t s);
 
 inline unsigned int blocks_for(long long n) { return (unsigned int)((n + kBlock - 1) / kBlock); }
+
+// ---- what the closure step needs of a single-grid context (api.hip) ----
+struct CtxView {
+    Geo geo;
+    MhdParams mp;
+    hipStream_t stream;
+    double* state;  // the current state in the canonical FP64 layout (FP64 adiabatic MHD only, else null)
+};
+CtxView ctx_view(mhd_ctx* c);
+// Recompute the context's CFL step from its current state (after a change in place).
+hipError_t ctx_refresh_cfl(mhd_ctx* c);
 
 }  // namespace mhd

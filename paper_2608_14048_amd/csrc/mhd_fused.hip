@@ -1,14 +1,16 @@
 // mhd_fused.hip -- one stage of the CT-MHD update on one periodic grid in two
 // z-marching kernels (bodies in mhd_tiles.hpp):
 //
-// k_flux3<RECON, RS>   one workgroup = a 64 x 4 tile of xy columns marching a chunk of
-//                      z planes; writes the 21 face fields and the 3 cell-E fields.
-// k_ct_update<CFL, IN> same tiling with 8 rows (one halo row per 8); edge EMFs, the
-//                      cell and face updates and, in the last stage, the CFL partials.
-//                      The FP64 kernel that also reduces the time step uses 4 rows: it
-//                      then keeps the previous plane's values in registers at three
-//                      workgroups per CU (with 8 rows they would cost it half its
-//                      occupancy).
+// k_flux3<RECON, RS, IN>  one workgroup = a TXF x TYF tile of xy columns marching a chunk
+//                         of z planes; Riemann solves on every face of the tile, the
+//                         cell fields of the stage output (rho, M, E), and the 9 face
+//                         fields + 3 cell-E fields the edge EMFs need.
+// k_ct_update<CFL, IN>    64-lane tiles of 8 rows (one halo row per 8); edge EMFs, the
+//                         face-field update and, in the last stage, the CFL partials.
+//                         The FP64 kernel that also reduces the time step uses 4 rows: it
+//                         then keeps the previous plane's values in registers at three
+//                         workgroups per CU (with 8 rows they would cost it half its
+//                         occupancy).
 #include "mhd_tiles.hpp"
 
 namespace mhd {
@@ -16,32 +18,32 @@ namespace mhd {
 using namespace tiles;
 
 namespace {
-constexpr int TX = 64;   // lanes along x
-constexpr int TY = 4;    // waves along y (flux kernel)
-constexpr int TY2 = 8;   // waves along y (CT/update kernel)
+constexpr int TXF = 16;  // lanes along x (flux/update kernel)
+constexpr int TYF = 16;  // rows (flux/update kernel)
+constexpr int TX = 64;   // lanes along x (CT kernel)
+constexpr int TY = 4;    // rows (FP64 CT kernel that reduces the time step)
+constexpr int TY2 = 8;   // rows (other CT kernels)
 }  // namespace
 
-// The FP64 PPM flux kernel is held to 168 registers, three waves per SIMD (the
-// workgroup memory of three workgroups fits a CU); its natural allocation gives two,
-// measured about 8 % slower.  Every other form keeps the compiler's choice (the same
-// request spills more there and measured slower).
+// Occupancy requests: none beyond two waves per SIMD for the FP64 PPM kernel.  Holding
+// it to three (168 registers) spills about 36 dwords per lane and measured 20 % slower
+// (3.48 against 2.91 ms per corrector launch at 256^3).
 template <int RECON, class R>
 struct FluxWaves {
-    static constexpr int min = RECON == 2 && sizeof(R) == 8 ? 3 : 1;
+    static constexpr int min = RECON == 2 && sizeof(R) == 8 ? 2 : 1;
 };
 
-template <int RECON, int RS, class R>
-__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(FluxWaves<RECON, R>::min)))
-void k_flux3(Geo g, MhdParams P, RegView<R> U, R* __restrict__ F, R* __restrict__ Rc, int kz,
-             unsigned int ntx, unsigned int nty, unsigned int nblk)
+template <int RECON, int RS, bool IN, class R>
+__global__ __launch_bounds__(TXF* TYF) __attribute__((amdgpu_waves_per_eu(FluxWaves<RECON, R>::min)))
+void k_flux3(Geo g, MhdParams P, StageArgs<R> a, int kz, unsigned int ntx, unsigned int nty, unsigned int nblk)
 {
-    using Tile = FluxTile<RECON, RS, R, TX, TY>;
+    using Tile = FluxTile<RECON, RS, IN, R, TXF, TYF>;
     __shared__ typename Tile::Lds lds;
     const unsigned int t = xcd_tile(blockIdx.x, nblk);
-    const int x0 = (int)(t % ntx) * TX;
-    const int y0 = (int)((t / ntx) % nty) * TY;
+    const int x0 = (int)(t % ntx) * TXF;
+    const int y0 = (int)((t / ntx) % nty) * TYF;
     const int k0 = (int)(t / (ntx * nty)) * kz;
-    Tile::run(g, P, U, F, Rc, x0, y0, k0, min(k0 + kz, g.nz), lds);
+    Tile::run(g, P, a, x0, y0, k0, min(k0 + kz, g.nz), lds);
 }
 
 template <bool CFL, bool IN, class R, int TYC>
@@ -112,43 +114,57 @@ FusedGrid fused_grid(const Geo& g, int kz)
 {
     FusedGrid fg;
     fg.kz = kz;
-    fg.ntx = (unsigned int)((g.nx + TX - 1) / TX);
-    fg.nty = (unsigned int)((g.ny + TY - 1) / TY);
+    fg.ntx = (unsigned int)((g.nx + TXF - 1) / TXF);
+    fg.nty = (unsigned int)((g.ny + TYF - 1) / TYF);
     fg.ntz = (unsigned int)((g.nz + kz - 1) / kz);
     fg.nblk = fg.ntx * fg.nty * fg.ntz;
-    fg.nty2 = (unsigned int)((g.ny + TY2 - 1) / TY2);
-    fg.nblk2 = fg.ntx * fg.nty2 * fg.ntz;
+    fg.ctx = (unsigned int)((g.nx + TX - 1) / TX);
+    fg.cty4 = (unsigned int)((g.ny + TY - 1) / TY);
+    fg.cty8 = (unsigned int)((g.ny + TY2 - 1) / TY2);
     return fg;
 }
 
-template <int RECON, int RS, class R>
-static hipError_t flux3(const Geo& g, const MhdParams& p, const FusedGrid& fg, void* U, void* F,
-                        void* Rc, hipStream_t s)
+int flux_tile_cells() { return TXF * TYF; }
+
+template <int RECON, int RS, bool IN, class R>
+static hipError_t flux3(const Geo& g, const MhdParams& p, const FusedGrid& fg, const StageArgs<R>& a,
+                        hipStream_t s)
 {
-    hipLaunchKernelGGL((k_flux3<RECON, RS, R>), dim3(fg.nblk), dim3(TX * TY), 0, s, g, p,
-                       reg_view<R>(U, g.n), (R*)F, (R*)Rc, fg.kz, fg.ntx, fg.nty, fg.nblk);
+    hipLaunchKernelGGL((k_flux3<RECON, RS, IN, R>), dim3(fg.nblk), dim3(TXF * TYF), 0, s, g, p, a, fg.kz,
+                       fg.ntx, fg.nty, fg.nblk);
     return hipGetLastError();
 }
 
-template <class R>
-static hipError_t flux3_any(const Geo& g, const MhdParams& p, const FusedGrid& fg, int recon,
-                            int riemann, void* U, void* F, void* Rc, hipStream_t s)
+template <int RECON, int RS, class R>
+static hipError_t flux3_in(const Geo& g, const MhdParams& p, const FusedGrid& fg, const StageArgs<R>& a,
+                           bool use_in, hipStream_t s)
 {
-    if (riemann == 1) {
-        if (recon == 0) return flux3<0, 1, R>(g, p, fg, U, F, Rc, s);
-        if (recon == 1) return flux3<1, 1, R>(g, p, fg, U, F, Rc, s);
-        return flux3<2, 1, R>(g, p, fg, U, F, Rc, s);
-    }
-    if (recon == 0) return flux3<0, 0, R>(g, p, fg, U, F, Rc, s);
-    if (recon == 1) return flux3<1, 0, R>(g, p, fg, U, F, Rc, s);
-    return flux3<2, 0, R>(g, p, fg, U, F, Rc, s);
+    return use_in ? flux3<RECON, RS, true, R>(g, p, fg, a, s) : flux3<RECON, RS, false, R>(g, p, fg, a, s);
 }
 
-hipError_t launch_mhd_flux3(const Geo& g, const MhdParams& p, const FusedGrid& fg, bool fp32,
-                            int recon, int riemann, void* U, void* F, void* Rc, hipStream_t s)
+template <class R>
+static hipError_t flux3_any(const Geo& g, const MhdParams& p, const FusedGrid& fg, int recon, int riemann,
+                            void* in, void* base, void* out, void* F, void* Rc, StageCoef coef, hipStream_t s)
 {
-    if (fp32) return flux3_any<float>(g, p, fg, recon, riemann, U, F, Rc, s);
-    return flux3_any<double>(g, p, fg, recon, riemann, U, F, Rc, s);
+    const StageArgs<R> a{reg_view<R>(in, g.n), reg_view<R>(base, g.n), reg_view<R>(out, g.n), (R*)F, (R*)Rc,
+                         coef};
+    const bool use_in = coef.g0 != 0.0 || p.gacc[0] != 0.0 || p.gacc[1] != 0.0 || p.gacc[2] != 0.0;
+    if (riemann == 1) {
+        if (recon == 0) return flux3_in<0, 1, R>(g, p, fg, a, use_in, s);
+        if (recon == 1) return flux3_in<1, 1, R>(g, p, fg, a, use_in, s);
+        return flux3_in<2, 1, R>(g, p, fg, a, use_in, s);
+    }
+    if (recon == 0) return flux3_in<0, 0, R>(g, p, fg, a, use_in, s);
+    if (recon == 1) return flux3_in<1, 0, R>(g, p, fg, a, use_in, s);
+    return flux3_in<2, 0, R>(g, p, fg, a, use_in, s);
+}
+
+hipError_t launch_mhd_flux3(const Geo& g, const MhdParams& p, const FusedGrid& fg, bool fp32, int recon,
+                            int riemann, void* in, void* base, void* out, void* F, void* Rc, StageCoef coef,
+                            hipStream_t s)
+{
+    if (fp32) return flux3_any<float>(g, p, fg, recon, riemann, in, base, out, F, Rc, coef, s);
+    return flux3_any<double>(g, p, fg, recon, riemann, in, base, out, F, Rc, coef, s);
 }
 
 template <class R>
@@ -158,26 +174,27 @@ static hipError_t ct_update(const Geo& g, const MhdParams& p, const FusedGrid& f
 {
     CtArgs<R> a{reg_view<R>(in, g.n), reg_view<R>(base, g.n), (const R*)F, (const R*)Rc,
                 reg_view<R>(out, g.n), partial, coef};
-    const bool use_in = coef.g0 != 0.0 || p.gacc[0] != 0.0 || p.gacc[1] != 0.0 || p.gacc[2] != 0.0;
-    const dim3 gr(fg.nblk2), bl(TX * TY2);
+    const bool use_in = coef.g0 != 0.0;
+    const unsigned int nb8 = fg.ctx * fg.cty8 * fg.ntz;
     if (dt_out) {
-        // FP64: 4-row tiles (the flux kernel's tiling); FP32: 8 rows
+        // FP64: 4-row tiles; FP32: 8 rows
         constexpr int TYC = sizeof(R) == 8 ? TY : TY2;
-        const unsigned int nty = sizeof(R) == 8 ? fg.nty : fg.nty2;
-        const unsigned int nblk = sizeof(R) == 8 ? fg.nblk : fg.nblk2;
+        const unsigned int nty = sizeof(R) == 8 ? fg.cty4 : fg.cty8;
+        const unsigned int nblk = fg.ctx * nty * fg.ntz;
         const dim3 grc(nblk), blc(TX * TYC);
         if (use_in)
-            hipLaunchKernelGGL((k_ct_update<true, true, R, TYC>), grc, blc, 0, s, g, p, a, fg.kz, fg.ntx, nty, nblk);
+            hipLaunchKernelGGL((k_ct_update<true, true, R, TYC>), grc, blc, 0, s, g, p, a, fg.kz, fg.ctx, nty, nblk);
         else
-            hipLaunchKernelGGL((k_ct_update<true, false, R, TYC>), grc, blc, 0, s, g, p, a, fg.kz, fg.ntx, nty, nblk);
+            hipLaunchKernelGGL((k_ct_update<true, false, R, TYC>), grc, blc, 0, s, g, p, a, fg.kz, fg.ctx, nty, nblk);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         return launch_min_final(partial, nblk, cfl_scale, dt_out, s);
     }
+    const dim3 gr(nb8), bl(TX * TY2);
     if (use_in)
-        hipLaunchKernelGGL((k_ct_update<false, true, R, TY2>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty2, fg.nblk2);
+        hipLaunchKernelGGL((k_ct_update<false, true, R, TY2>), gr, bl, 0, s, g, p, a, fg.kz, fg.ctx, fg.cty8, nb8);
     else
-        hipLaunchKernelGGL((k_ct_update<false, false, R, TY2>), gr, bl, 0, s, g, p, a, fg.kz, fg.ntx, fg.nty2, fg.nblk2);
+        hipLaunchKernelGGL((k_ct_update<false, false, R, TY2>), gr, bl, 0, s, g, p, a, fg.kz, fg.ctx, fg.cty8, nb8);
     return hipGetLastError();
 }
 

@@ -2,22 +2,23 @@
 // templates on the tile shape, shared by the single-grid kernels (mhd_fused.hip) and
 // the batched meshblock kernels (batch.hip).
 //
-// FluxTile<RECON, RS, R, TX, TY>: for each z plane of the tile's chunk the primitives
-//   (floors applied, B_cc the mean of the two bounding faces) of the tile and its x/y
-//   halo are staged once in LDS; the z stencil of each column lives in a per-thread
-//   register window.  Every cell solves the Riemann problem on its three left faces
-//   (x, y, z) -- reconstruction of the face-frame primitives (rho, v_n, v_t1, v_t2, p,
-//   B_t1, B_t2), HLLE or HLLD -- and writes, per face, the mass, momentum and energy
-//   fluxes in the global frame plus the two face values of the electric field
-//   (E_t1 = F(B_t2), E_t2 = -F(B_t1)), and the cell-centred field E = -v x B.
+// FluxTile<RECON, RS, IN, R, TX, TY>: for each z plane of the tile's chunk the
+//   primitives (floors applied, B_cc the mean of the two bounding faces) of the tile and
+//   its x/y halo are staged once in LDS; the z stencil of each column lives in a
+//   per-thread register window.  The Riemann problems (reconstruction of the face-frame
+//   primitives (rho, v_n, v_t1, v_t2, p, B_t1, B_t2), HLLE or HLLD) are solved on every
+//   face the tile's cells touch; their mass, momentum and energy fluxes meet in LDS and
+//   the cell fields are updated in the same pass (flux divergence of eq. (fv_update),
+//   sources, the two-register combination out = g0 in + g1 base + bdt L).  What the
+//   edge EMFs need leaves the kernel: per face the mass flux and the two face values of
+//   the electric field (E_t1 = F(B_t2), E_t2 = -F(B_t1)), per cell E = -v x B.
 //
 // CtTile<CFL, IN, R, TX, TY>: per plane the Gardiner-Stone upwind edge EMFs E_z of the
 //   plane and E_x, E_y of the level above are built in LDS from the face values, the
-//   cell field and the mass-flux signs; the cell is updated with the flux divergence of
-//   eq. (fv_update) plus sources, its faces with -curl E of eq. (ct), both in the
-//   two-register form out = g0 in + g1 base + bdt L.  With CFL the time step of
-//   eq. (cfl) is taken over the updated state in the same pass (the updated right-hand
-//   faces needed for B_cc come from the same edge values).
+//   cell field and the mass-flux signs; the faces are updated with -curl E of eq. (ct)
+//   in the same two-register form.  With CFL the time step of eq. (cfl) is taken over
+//   the updated state in the same pass (the updated right-hand faces needed for B_cc
+//   come from the same edge values; the cell fields from the flux/update kernel).
 //
 // Precision: templated on the real type R.  R = double is the FP64 path.  R = float is
 // the FP32-bulk form: density, momenta, face fields, reconstruction, Riemann solves, CT
@@ -141,9 +142,9 @@ __device__ __forceinline__ void solve(const Prim7<R>& L, const Prim7<R>& Rt, R b
 
 // Reconstruction along z as a pipeline over the planes a column visits: each new plane
 // costs one slope, one interface and one limiter (PPM), one slope (PLM) or nothing (DC).
-// push(ak, a) takes the value of plane k (read back from the staged plane, so it is not
-// carried in registers) and the value of plane k + AHEAD, and returns the two states on
-// the face k - 1/2.
+// push(ak, a) takes the value of plane k (loaded again rather than carried in
+// registers) and the value of plane k + AHEAD, and returns the two states on the face
+// k - 1/2.
 template <int RECON, class R>
 struct ZPipe;
 
@@ -215,132 +216,284 @@ struct ZPipe<2, R> {
     }
 };
 
-// One tile of the flux kernel: TX x TY cells of every plane k0 <= k < k1 (the tile may
-// reach past the grid edge; such cells only stage halos).  Threads: TX * TY, lanes
-// along x first.
-template <int RECON, int RS, class R, int TX, int TY>
+// Stage-kernel arguments: fluxes of `in`; out = g0 in + g1 base + bdt L(in) for the
+// cell fields (rho, M, E), written by FluxTile; the face fields are updated by CtTile
+// from the edge EMFs that the face values written to F and Rc give.
+template <class R>
+struct StageArgs {
+    RegView<R> in;    // stage input register
+    RegView<R> base;  // second register; may equal in, never out
+    RegView<R> out;   // distinct from in and base
+    R* F;             // 9 face fields: x (mass flux, E_y, E_z), y (mass flux, E_z, E_x),
+                      // z (mass flux, E_x, E_y), each face with the cell on its high side
+    R* Rc;            // 3 cell fields E = -v x B
+    StageCoef co;
+};
+
+// Field q of the 9 face fields F (direction-major).
+enum FaceField { FX_MASS = 0, FX_EY, FX_EZ, FY_MASS, FY_EZ, FY_EX, FZ_MASS, FZ_EX, FZ_EY, NFACE };
+
+// One tile of the flux/update kernel: TX x TY cells of every plane k0 <= k < k1 (the tile
+// may reach past the grid edge).  Threads: TX * TY, lanes along x first.  Per plane:
+//  - the primitives of the tile and its x/y halo are staged in LDS (one more column and
+//    row on the high side than the cells need: the tile's high faces);
+//  - every thread solves its cell's low x and y faces and the z face above its cell (the
+//    z stencil is a register pipeline fed one plane ahead); threads 0 .. TX+TY-1 also
+//    solve the tile's high faces (the row above it, the column right of it);
+//  - the faces' mass, momentum and energy fluxes meet in LDS, and every cell gets the
+//    flux divergence of eq. (fv_update) plus sources and the stage combination, in the
+//    same arithmetic as a separate update pass would use;
+//  - the face values of E and the mass fluxes the edge EMFs need go to F, E = -v x B of
+//    the cell to Rc.
+template <int RECON, int RS, bool IN, class R, int TX, int TY>
 struct FluxTile {
     static constexpr int SL = Stencil<RECON>::L, SR = Stencil<RECON>::R;
-    static constexpr int LX = TX + SL + SR, LY = TY + SL + SR;
+    static constexpr int LX = TX + SL + SR + 1, LY = TY + SL + SR + 1;
+    static constexpr int NT = TX * TY, NR = TX + TY;
+    static_assert(NR <= NT, "the tile's high faces need TX + TY threads");
     // FP64 PPM: keep the compiler from hoisting the stencil loads of every variable
     // ahead of the reconstructions (it would hold them all in registers at once)
     static constexpr bool kFence = RECON == 2 && sizeof(R) == 8;
     struct Lds {
-        R sw[8][LY][LX];
+        R sw[8][LY][LX];         // primitives of the plane
+        R hx[5][TY][TX + 1];     // fluxes through the x faces of the plane's rows
+        R hy[5][TY + 1][TX];     // fluxes through the y faces of the plane's columns
     };
-    __device__ static void run(const Geo& g, const MhdParams& P, const RegView<R>& U, R* __restrict__ F,
-                               R* __restrict__ Rc, int x0, int y0, int k0, int k1, Lds& lds)
+
+    // Face states of the seven face-frame variables from a stencil line in LDS: `at(v, s)`
+    // gives staged variable v at offset s from the face's high-side cell.
+    template <class At>
+    __device__ static void recon7(const int comp[7], At at, Prim7<R>& L, Prim7<R>& Rt)
+    {
+        R* lr[7][2] = {{&L.d, &Rt.d}, {&L.vn, &Rt.vn}, {&L.vt1, &Rt.vt1}, {&L.vt2, &Rt.vt2},
+                       {&L.p, &Rt.p}, {&L.bt1, &Rt.bt1}, {&L.bt2, &Rt.bt2}};
+        R st[6];
+    #pragma unroll
+        for (int v = 0; v < 7; ++v) {
+    #pragma unroll
+            for (int s = -SL; s <= SR; ++s) st[3 + s] = at(comp[v], s);
+            face_states<RECON>(st, *lr[v][0], *lr[v][1]);
+            if constexpr (kFence) __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+
+    __device__ static void run(const Geo& g, const MhdParams& P, const StageArgs<R>& a, int x0, int y0,
+                               int k0, int k1, Lds& lds)
     {
         using Pipe = ZPipe<RECON, R>;
         auto& sw = lds.sw;
         const int lane = (int)threadIdx.x % TX, row = (int)threadIdx.x / TX;
         const int i = x0 + lane, j = y0 + row;
         const bool live = i < g.nx && j < g.ny;
-        const int ic = live ? i : 0, jc = live ? j : 0;
+        // this thread's cell, taken periodically (a lane or row just past the grid edge
+        // owns the face at the edge, which is the face at 0)
+        const int ic = wrap_any(i, g.nx), jc = wrap_any(j, g.ny);
+        // the low faces this thread solves: those of live rows/columns and the grid's
+        // high edge when the tile reaches past it
+        const bool xneed = i <= g.nx && j < g.ny;
+        const bool yneed = j <= g.ny && i < g.nx;
         const long long n = g.n;
-        const unsigned int plane = (unsigned int)g.nx * (unsigned int)g.ny;
-        R* Fo[21];
+        const unsigned int nx = g.nx, plane = (unsigned int)g.nx * (unsigned int)g.ny;
+        R* Fo[NFACE];
     #pragma unroll
-        for (int q = 0; q < 21; ++q) Fo[q] = F + q * n;
+        for (int q = 0; q < NFACE; ++q) Fo[q] = a.F + q * n;
+        // the tile's own high faces: threads q < TX take the y face above column q, threads
+        // TX <= q < TX + TY the x face right of row q - TX (when inside the grid's range)
+        const int q = (int)threadIdx.x;
+        const bool ring_y = q < TX, ring_x = !ring_y && q < NR;
+        const int rq = ring_y ? q : q - TX;
+        const bool rneed = ring_y ? (y0 + TY <= g.ny && x0 + rq < g.nx) : (ring_x && x0 + TX <= g.nx && y0 + rq < g.ny);
+        const int rxc = ring_y ? wrap_any(x0 + rq, g.nx) : wrap_any(x0 + TX, g.nx);
+        const int ryc = ring_y ? wrap_any(y0 + TY, g.ny) : wrap_any(y0 + rq, g.ny);
 
-        // z pipeline of the face-frame variables (rho, v_z, v_x, v_y, p, B_x, B_y)
+        // z pipeline of the face-frame variables (rho, v_z, v_x, v_y, p, B_x, B_y); plane
+        // k's own values come from the staged plane (a direct load on the last pass)
         Pipe zp[7];
         {
             R pre[7][Pipe::PRIME];
     #pragma unroll
             for (int s = 0; s < Pipe::PRIME; ++s) {
-                const Prim8<R> w = load_prims(g, P, U, ic, jc, wrap_any(k0 - Pipe::PRIME + Pipe::AHEAD + s, g.nz));
+                const Prim8<R> w = load_prims(g, P, a.in, ic, jc, wrap_any(k0 - Pipe::PRIME + Pipe::AHEAD + s, g.nz));
                 pre[0][s] = w.d; pre[1][s] = w.vz; pre[2][s] = w.vx; pre[3][s] = w.vy;
                 pre[4][s] = w.p; pre[5][s] = w.bx; pre[6][s] = w.by;
             }
     #pragma unroll
             for (int v = 0; v < 7; ++v) zp[v].prime(pre[v]);
         }
+        const double bdt = a.co.bdt, g0 = a.co.g0, g1 = a.co.g1;
+        const R bdtr = R(bdt), g0r = R(g0), g1r = R(g1);
+        const R idx = R(g.inv_dx[0]), idy = R(g.inv_dx[1]), idz = R(g.inv_dx[2]);
+        // carried from one plane to the next: the x/y part of the flux divergence of the
+        // cell below (mass and momenta in R, energy in FP64) and the z flux through its
+        // low face (mass, M_x, M_y, M_z, E)
+        R acc[4], fzp[5];
+        double accE = 0.0;
+    #pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = R(0);
+    #pragma unroll
+        for (int v = 0; v < 5; ++v) fzp[v] = R(0);
 
-        for (int k = k0; k < k1; ++k) {
-            // stage the primitives of plane k (tile + x/y halos, corners skipped); the
-            // staging waves get issue priority so their loads go out ahead of the
-            // arithmetic of the other workgroups on the CU
-            __builtin_amdgcn_s_setprio(1);
-            for (int q = threadIdx.x; q < LX * LY; q += TX * TY) {
-                const int r = q / LX, cc = q - r * LX;
-                const bool xh = cc < SL || cc >= SL + TX, yh = r < SL || r >= SL + TY;
-                if (xh && yh) continue;
-                const int gx = wrap_any(x0 + cc - SL, g.nx), gy = wrap_any(y0 + r - SL, g.ny);
-                const Prim8<R> w = load_prims(g, P, U, gx, gy, k);
-                sw[0][r][cc] = w.d; sw[1][r][cc] = w.vx; sw[2][r][cc] = w.vy; sw[3][r][cc] = w.vz;
-                sw[4][r][cc] = w.p; sw[5][r][cc] = w.bx; sw[6][r][cc] = w.by; sw[7][r][cc] = w.bz;
+        // pass k solves the z face k - 1/2 and completes the cell of plane k - 1, then
+        // (k < k1) solves the x and y faces of plane k; the pass k = k1 only completes
+        // the chunk's last cell
+        for (int k = k0; k <= k1; ++k) {
+            const bool full = k < k1;
+            Prim8<R> wk{}, wz{};
+            if (full) {
+                // stage the primitives of plane k (tile + x/y halos, corners skipped); the
+                // staging waves get issue priority so their loads go out ahead of the
+                // arithmetic of the other workgroups on the CU
+                __builtin_amdgcn_s_setprio(1);
+                for (int t = threadIdx.x; t < LX * LY; t += NT) {
+                    const int r = t / LX, cc = t - r * LX;
+                    const bool xh = cc < SL || cc >= SL + TX, yh = r < SL || r >= SL + TY;
+                    if (xh && yh) continue;
+                    const int gx = wrap_any(x0 + cc - SL, g.nx), gy = wrap_any(y0 + r - SL, g.ny);
+                    const Prim8<R> w = load_prims(g, P, a.in, gx, gy, k);
+                    sw[0][r][cc] = w.d; sw[1][r][cc] = w.vx; sw[2][r][cc] = w.vy; sw[3][r][cc] = w.vz;
+                    sw[4][r][cc] = w.p; sw[5][r][cc] = w.bx; sw[6][r][cc] = w.by; sw[7][r][cc] = w.bz;
+                }
+            } else if constexpr (RECON != 1) {
+                wk = load_prims(g, P, a.in, ic, jc, wrap_any(k, g.nz));
             }
-            // newest plane of the z pipeline (donor cell needs none beyond the staged one)
-            Prim8<R> wz{};
-            if constexpr (Pipe::AHEAD > 0) wz = load_prims(g, P, U, ic, jc, wrap_any(k + Pipe::AHEAD, g.nz));
-            __syncthreads();
-            __builtin_amdgcn_s_setprio(0);
+            // newest plane of the z pipeline (donor cell needs none beyond plane k)
+            if constexpr (Pipe::AHEAD > 0) wz = load_prims(g, P, a.in, ic, jc, wrap_any(k + Pipe::AHEAD, g.nz));
+            if (full) {
+                __syncthreads();
+                __builtin_amdgcn_s_setprio(0);
+            }
 
-            const unsigned int c = (unsigned int)k * plane + (unsigned int)jc * g.nx + ic;
-            R st[6];
+            const unsigned int kk = (unsigned int)(k < g.nz ? k : k - g.nz);
+            const unsigned int c = kk * plane + (unsigned int)jc * nx + (unsigned int)ic;
             Prim7<R> L, Rt;
             Flux7<R> f;
-            // ---- z faces from the pipeline: (rho, vz, vx, vy, p, Bx, By)
+            // ---- z face k - 1/2 from the pipeline: (rho, vz, vx, vy, p, Bx, By)
             {
                 const int r0 = row + SL, c0 = lane + SL;
-                zp[0].push(sw[0][r0][c0], wz.d, L.d, Rt.d);
-                zp[1].push(sw[3][r0][c0], wz.vz, L.vn, Rt.vn);
-                zp[2].push(sw[1][r0][c0], wz.vx, L.vt1, Rt.vt1);
-                zp[3].push(sw[2][r0][c0], wz.vy, L.vt2, Rt.vt2);
-                zp[4].push(sw[4][r0][c0], wz.p, L.p, Rt.p);
-                zp[5].push(sw[5][r0][c0], wz.bx, L.bt1, Rt.bt1);
-                zp[6].push(sw[6][r0][c0], wz.by, L.bt2, Rt.bt2);
+                zp[0].push(full ? sw[0][r0][c0] : wk.d, wz.d, L.d, Rt.d);
+                zp[1].push(full ? sw[3][r0][c0] : wk.vz, wz.vz, L.vn, Rt.vn);
+                zp[2].push(full ? sw[1][r0][c0] : wk.vx, wz.vx, L.vt1, Rt.vt1);
+                zp[3].push(full ? sw[2][r0][c0] : wk.vy, wz.vy, L.vt2, Rt.vt2);
+                zp[4].push(full ? sw[4][r0][c0] : wk.p, wz.p, L.p, Rt.p);
+                zp[5].push(full ? sw[5][r0][c0] : wk.bx, wz.bx, L.bt1, Rt.bt1);
+                zp[6].push(full ? sw[6][r0][c0] : wk.by, wz.by, L.bt2, Rt.bt2);
             }
             if (live) {
-                solve<RS>(L, Rt, ldT(U.b[2], c), P, f);
-                stT(Fo[14], c, f.d); stT(Fo[17], c, f.mn); stT(Fo[15], c, f.mt1); stT(Fo[16], c, f.mt2);
-                stT(Fo[18], c, f.e); stT(Fo[19], c, f.bt2); stT(Fo[20], c, -f.bt1);
+                solve<RS>(L, Rt, ldT(a.in.b[2], c), P, f);
+                const R fz[5] = {f.d, f.mt1, f.mt2, f.mn, f.e};
+                // the face's E values and mass flux, stored with the cell above it (the
+                // chunk's first face is stored by the chunk below, as its last)
+                if (k > k0) {
+    #pragma clang fp contract(off)
+                    stT(Fo[FZ_MASS], c, f.d); stT(Fo[FZ_EX], c, f.bt2); stT(Fo[FZ_EY], c, -f.bt1);
+                    // ---- the cell of plane k - 1: flux divergence (density and momenta
+                    // in R, energy in FP64), sources of a constant gas acceleration, the
+                    // stage combination
+                    const unsigned int cb = (unsigned int)(k - 1) * plane + (unsigned int)jc * nx + (unsigned int)ic;
+                    R Lc[4];
+    #pragma unroll
+                    for (int v = 0; v < 4; ++v) Lc[v] = -(acc[v] + (fz[v] - fzp[v]) * idz);
+                    double LE = -(accE + ((double)fz[4] - (double)fzp[4]) * g.inv_dx[2]);
+                    R o[4];
+                    double oE;
+                    if (IN) {
+                        const R rho_in = ldT(a.in.rho, cb);
+                        const R m_in[3] = {ldT(a.in.m[0], cb), ldT(a.in.m[1], cb), ldT(a.in.m[2], cb)};
+                        Lc[1] += rho_in * R(P.gacc[0]);
+                        Lc[2] += rho_in * R(P.gacc[1]);
+                        Lc[3] += rho_in * R(P.gacc[2]);
+                        LE += ((double)m_in[0] * P.gacc[0] + (double)m_in[1] * P.gacc[1]) + (double)m_in[2] * P.gacc[2];
+                        o[0] = (g0r * rho_in + g1r * ldT(a.base.rho, cb)) + bdtr * Lc[0];
+    #pragma unroll
+                        for (int v = 0; v < 3; ++v) o[1 + v] = (g0r * m_in[v] + g1r * ldT(a.base.m[v], cb)) + bdtr * Lc[1 + v];
+                        oE = (g0 * ldT(a.in.E, cb) + g1 * ldT(a.base.E, cb)) + bdt * LE;
+                    } else {
+                        o[0] = g1r * ldT(a.base.rho, cb) + bdtr * Lc[0];
+    #pragma unroll
+                        for (int v = 0; v < 3; ++v) o[1 + v] = g1r * ldT(a.base.m[v], cb) + bdtr * Lc[1 + v];
+                        oE = g1 * ldT(a.base.E, cb) + bdt * LE;
+                    }
+                    // out never aliases in or base (the host rotates three registers)
+                    stT(a.out.rho, cb, o[0]);
+    #pragma unroll
+                    for (int v = 0; v < 3; ++v) stT(a.out.m[v], cb, o[1 + v]);
+                    stT(a.out.E, cb, oE);
+                }
+    #pragma unroll
+                for (int v = 0; v < 5; ++v) fzp[v] = fz[v];
+            }
+            if (!full) break;
+            if constexpr (kFence) __builtin_amdgcn_sched_barrier(0);
+            // ---- x face (low face of the cell): (rho, vx, vy, vz, p, By, Bz)
+            if (xneed) {
+                const int comp[7] = {0, 1, 2, 3, 4, 6, 7};
+                recon7(comp, [&](int v, int s) { return sw[v][row + SL][lane + SL + s]; }, L, Rt);
+                solve<RS>(L, Rt, ldT(a.in.b[0], c), P, f);
+                lds.hx[0][row][lane] = f.d; lds.hx[1][row][lane] = f.mn; lds.hx[2][row][lane] = f.mt1;
+                lds.hx[3][row][lane] = f.mt2; lds.hx[4][row][lane] = f.e;
+                if (live) {
+                    stT(Fo[FX_MASS], c, f.d); stT(Fo[FX_EY], c, f.bt2); stT(Fo[FX_EZ], c, -f.bt1);
+                }
                 if constexpr (kFence) __builtin_amdgcn_sched_barrier(0);
-                // ---- x faces: (rho, vx, vy, vz, p, By, Bz)
-                {
-                    const int comp[7] = {0, 1, 2, 3, 4, 6, 7};
-                    R* lr[7][2] = {{&L.d, &Rt.d}, {&L.vn, &Rt.vn}, {&L.vt1, &Rt.vt1}, {&L.vt2, &Rt.vt2},
-                                   {&L.p, &Rt.p}, {&L.bt1, &Rt.bt1}, {&L.bt2, &Rt.bt2}};
-    #pragma unroll
-                    for (int v = 0; v < 7; ++v) {
-    #pragma unroll
-                        for (int s = -SL; s <= SR; ++s) st[3 + s] = sw[comp[v]][row + SL][lane + SL + s];
-                        face_states<RECON>(st, *lr[v][0], *lr[v][1]);
-                        if constexpr (kFence) __builtin_amdgcn_sched_barrier(0);
-                    }
-                    solve<RS>(L, Rt, ldT(U.b[0], c), P, f);
-                    stT(Fo[0], c, f.d); stT(Fo[1], c, f.mn); stT(Fo[2], c, f.mt1); stT(Fo[3], c, f.mt2);
-                    stT(Fo[4], c, f.e); stT(Fo[5], c, f.bt2); stT(Fo[6], c, -f.bt1);
-                    if constexpr (kFence) __builtin_amdgcn_sched_barrier(0);
+            }
+            // ---- y face: (rho, vy, vz, vx, p, Bz, Bx)
+            if (yneed) {
+                const int comp[7] = {0, 2, 3, 1, 4, 7, 5};
+                recon7(comp, [&](int v, int s) { return sw[v][row + SL + s][lane + SL]; }, L, Rt);
+                solve<RS>(L, Rt, ldT(a.in.b[1], c), P, f);
+                lds.hy[0][row][lane] = f.d; lds.hy[1][row][lane] = f.mt2; lds.hy[2][row][lane] = f.mn;
+                lds.hy[3][row][lane] = f.mt1; lds.hy[4][row][lane] = f.e;
+                if (live) {
+                    stT(Fo[FY_MASS], c, f.d); stT(Fo[FY_EZ], c, f.bt2); stT(Fo[FY_EX], c, -f.bt1);
                 }
-                // ---- y faces: (rho, vy, vz, vx, p, Bz, Bx)
-                {
+                if constexpr (kFence) __builtin_amdgcn_sched_barrier(0);
+            }
+            // ---- cell field E = -v x B (rounded as written, as is every expression that
+            // pairs x and y terms, so that the step keeps the swap of x and y exact)
+            if (live) {
+    #pragma clang fp contract(off)
+                const R vx = sw[1][row + SL][lane + SL], vy = sw[2][row + SL][lane + SL];
+                const R vz = sw[3][row + SL][lane + SL], bx = sw[5][row + SL][lane + SL];
+                const R by = sw[6][row + SL][lane + SL], bz = sw[7][row + SL][lane + SL];
+                stT(a.Rc, c, vz * by - vy * bz);
+                stT(a.Rc + n, c, vx * bz - vz * bx);
+                stT(a.Rc + 2 * n, c, vy * bx - vx * by);
+            }
+            // ---- the tile's high faces (fluxes only: their E values belong to the
+            // neighbouring tile's cells)
+            if (rneed) {
+                const unsigned int cr = (unsigned int)k * plane + (unsigned int)ryc * nx + (unsigned int)rxc;
+                if (ring_y) {
                     const int comp[7] = {0, 2, 3, 1, 4, 7, 5};
-                    R* lr[7][2] = {{&L.d, &Rt.d}, {&L.vn, &Rt.vn}, {&L.vt1, &Rt.vt1}, {&L.vt2, &Rt.vt2},
-                                   {&L.p, &Rt.p}, {&L.bt1, &Rt.bt1}, {&L.bt2, &Rt.bt2}};
-    #pragma unroll
-                    for (int v = 0; v < 7; ++v) {
-    #pragma unroll
-                        for (int s = -SL; s <= SR; ++s) st[3 + s] = sw[comp[v]][row + SL + s][lane + SL];
-                        face_states<RECON>(st, *lr[v][0], *lr[v][1]);
-                        if constexpr (kFence) __builtin_amdgcn_sched_barrier(0);
-                    }
-                    solve<RS>(L, Rt, ldT(U.b[1], c), P, f);
-                    stT(Fo[7], c, f.d); stT(Fo[9], c, f.mn); stT(Fo[10], c, f.mt1); stT(Fo[8], c, f.mt2);
-                    stT(Fo[11], c, f.e); stT(Fo[12], c, f.bt2); stT(Fo[13], c, -f.bt1);
-                }
-                // ---- cell field E = -v x B
-                {
-                    const R vx = sw[1][row + SL][lane + SL], vy = sw[2][row + SL][lane + SL];
-                    const R vz = sw[3][row + SL][lane + SL], bx = sw[5][row + SL][lane + SL];
-                    const R by = sw[6][row + SL][lane + SL], bz = sw[7][row + SL][lane + SL];
-                    stT(Rc, c, vz * by - vy * bz);
-                    stT(Rc + n, c, vx * bz - vz * bx);
-                    stT(Rc + 2 * n, c, vy * bx - vx * by);
+                    recon7(comp, [&](int v, int s) { return sw[v][TY + SL + s][rq + SL]; }, L, Rt);
+                    solve<RS>(L, Rt, ldT(a.in.b[1], cr), P, f);
+                    lds.hy[0][TY][rq] = f.d; lds.hy[1][TY][rq] = f.mt2; lds.hy[2][TY][rq] = f.mn;
+                    lds.hy[3][TY][rq] = f.mt1; lds.hy[4][TY][rq] = f.e;
+                } else {
+                    const int comp[7] = {0, 1, 2, 3, 4, 6, 7};
+                    recon7(comp, [&](int v, int s) { return sw[v][rq + SL][TX + SL + s]; }, L, Rt);
+                    solve<RS>(L, Rt, ldT(a.in.b[0], cr), P, f);
+                    lds.hx[0][rq][TX] = f.d; lds.hx[1][rq][TX] = f.mn; lds.hx[2][rq][TX] = f.mt1;
+                    lds.hx[3][rq][TX] = f.mt2; lds.hx[4][rq][TX] = f.e;
                 }
             }
             __syncthreads();
+            // ---- the x/y part of this cell's flux divergence, carried to the next pass
+            if (live) {
+    #pragma clang fp contract(off)
+    #pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const R fx = (lds.hx[v][row][lane + 1] - lds.hx[v][row][lane]) * idx;
+                    const R fy = (lds.hy[v][row + 1][lane] - lds.hy[v][row][lane]) * idy;
+                    acc[v] = fx + fy;
+                }
+                const double fx = ((double)lds.hx[4][row][lane + 1] - (double)lds.hx[4][row][lane]) * g.inv_dx[0];
+                const double fy = ((double)lds.hy[4][row + 1][lane] - (double)lds.hy[4][row][lane]) * g.inv_dx[1];
+                accE = fx + fy;
+            }
+            // no barrier here: the next plane's staging writes only the primitives, which
+            // every thread finished reading before the barrier above, and the fluxes are
+            // rewritten only after the next barrier
         }
     }
 };
@@ -368,17 +521,18 @@ template <class R>
 struct CtArgs {
     RegView<R> in;       // stage input register
     RegView<R> base;     // second register; may equal in, never out
-    const R* F;          // 3 x 7 face fields
+    const R* F;          // the 9 face fields of FaceField
     const R* Rc;         // 3 cell E fields
-    RegView<R> out;      // distinct from in and base
+    RegView<R> out;      // distinct from in and base; its cell fields are already updated
     double* partial;     // CFL partial minima, one per workgroup
     StageCoef co;
 };
 
-// One tile of the CT/update kernel (TX x TY cells, planes k0 <= k < k1); returns this
-// thread's CFL minimum of the updated state (INFINITY unless CFL).  CFL: reduce the
-// time step of the output.  IN: the stage reads its input register (g0 != 0 or a gas
-// acceleration is set); otherwise only the base register is read.
+// One tile of the CT kernel (TX x TY cells, planes k0 <= k < k1); returns this thread's
+// CFL minimum of the updated state (INFINITY unless CFL).  CFL: reduce the time step of
+// the output (its cell fields come from the flux/update kernel of the same stage).  IN:
+// the stage reads its input register's face fields (g0 != 0); otherwise only the base
+// register's.
 template <bool CFL, bool IN, class R, int TX, int TY>
 struct CtTile {
     // edges held for the tile: E_z on plane k, E_x / E_y on levels k-1/2 (slot lv^1)
@@ -399,9 +553,9 @@ struct CtTile {
         const bool live = i < g.nx && j < g.ny;
         const long long n = g.n;
         const unsigned int nx = g.nx, plane = (unsigned int)g.nx * (unsigned int)g.ny;
-        const R* Fb[21];
+        const R* Fb[NFACE];
     #pragma unroll
-        for (int q = 0; q < 21; ++q) Fb[q] = a.F + q * n;
+        for (int q = 0; q < NFACE; ++q) Fb[q] = a.F + q * n;
         const R* Rx = a.Rc;
         const R* Ry = a.Rc + n;
         const R* Rz = a.Rc + 2 * n;
@@ -413,20 +567,19 @@ struct CtTile {
         auto edge_z = [&](int x, int y, int z) -> R {
             const int xm = wrap_once(x - 1, g.nx), ym = wrap_once(y - 1, g.ny);
             const unsigned int c = at(x, y, z), cx = at(xm, y, z), cy = at(x, ym, z), cxy = at(xm, ym, z);
-            // p = x, q = y: X on x-faces (slot 6 of x), Y on y-faces (slot 5 of y)
-            return gs_edge(ldT(Fb[6], c), ldT(Fb[6], cy), ldT(Fb[12], c), ldT(Fb[12], cx),
+            // p = x, q = y: X on x-faces, Y on y-faces
+            return gs_edge(ldT(Fb[FX_EZ], c), ldT(Fb[FX_EZ], cy), ldT(Fb[FY_EZ], c), ldT(Fb[FY_EZ], cx),
                            ldT(Rz, c), ldT(Rz, cx), ldT(Rz, cy), ldT(Rz, cxy),
-                           ldT(Fb[0], c), ldT(Fb[0], cy), ldT(Fb[7], c), ldT(Fb[7], cx));
+                           ldT(Fb[FX_MASS], c), ldT(Fb[FX_MASS], cy), ldT(Fb[FY_MASS], c), ldT(Fb[FY_MASS], cx));
         };
         // Level edges E_x, E_y at z-level zl - 1/2 for the tile (+1 ring on the high side).
         // A thread keeps the same edge positions on every level, so the values of plane
         // zl - 1 that a level needs are the plane-zl values the level below read: they
         // stay in registers (cx*, cy*) instead of coming back from memory, for the
-        // first NC edge positions of the thread.  Likewise the z fluxes of the high face
-        // (fzc) and, with CFL, the updated B_z of the high face (b3c) carry over to the
-        // plane above.  An FP64 kernel that also reduces the time step on tiles taller
-        // than 4 rows carries nothing: at 512 threads the extra registers would cost it
-        // half its occupancy, which it needs more.
+        // first NC edge positions of the thread.  With CFL the updated B_z of the high
+        // face (b3c) carries over to the plane above.  An FP64 kernel that also reduces
+        // the time step on tiles taller than 4 rows carries nothing: at 512 threads the
+        // extra registers would cost it half its occupancy, which it needs more.
         constexpr int NT = TX * TY, NE = (TX + 1) * (TY + 1), NQ = (NE + NT - 1) / NT;
         constexpr bool ZC = !(CFL && sizeof(R) == 8 && TY > 4);
         constexpr int NC = !ZC ? 0 : (sizeof(R) == 4 ? NQ : 1);
@@ -447,39 +600,37 @@ struct CtTile {
                 if (q >= NE || gx > g.nx || gy > g.ny) continue;
                 const int wx = gx == g.nx ? 0 : gx, wy = gy == g.ny ? 0 : gy;
                 if (cc < TX && gx < g.nx) {
-                    // E_x at (x, y-1/2, z-1/2); p = y, q = z: X on y-faces (slot 6 of the
-                    // y sweep), Y on z-faces (slot 5 of z)
+                    // E_x at (x, y-1/2, z-1/2); p = y, q = z: X on y-faces, Y on z-faces
                     const int ym = wrap_once(wy - 1, g.ny);
                     const unsigned int c = at(wx, wy, zz), cy = at(wx, ym, zz);
                     const int mc = m < NA ? m : 0;
                     R Xm = cx13[mc], R0m = crx0[mc], Rmm = crxm[mc], fpm = cx7[mc];  // plane zl - 1
                     if (first || m >= NC) {
                         const unsigned int cz = at(wx, wy, zm), cyz = at(wx, ym, zm);
-                        Xm = ldT(Fb[13], cz); R0m = ldT(Rx, cz);
-                        Rmm = ldT(Rx, cyz); fpm = ldT(Fb[7], cz);
+                        Xm = ldT(Fb[FY_EX], cz); R0m = ldT(Rx, cz);
+                        Rmm = ldT(Rx, cyz); fpm = ldT(Fb[FY_MASS], cz);
                     }
-                    const R X0 = ldT(Fb[13], c), R00 = ldT(Rx, c), Rm0 = ldT(Rx, cy), fp0 = ldT(Fb[7], c);
-                    sEx[slot][r][cc] = gs_edge(X0, Xm, ldT(Fb[19], c), ldT(Fb[19], cy), R00, Rm0, R0m, Rmm, fp0,
-                                               fpm, ldT(Fb[14], c), ldT(Fb[14], cy));
+                    const R X0 = ldT(Fb[FY_EX], c), R00 = ldT(Rx, c), Rm0 = ldT(Rx, cy), fp0 = ldT(Fb[FY_MASS], c);
+                    sEx[slot][r][cc] = gs_edge(X0, Xm, ldT(Fb[FZ_EX], c), ldT(Fb[FZ_EX], cy), R00, Rm0, R0m, Rmm,
+                                               fp0, fpm, ldT(Fb[FZ_MASS], c), ldT(Fb[FZ_MASS], cy));
                     if (m < NC) {
                         cx13[mc] = X0; crx0[mc] = R00; crxm[mc] = Rm0; cx7[mc] = fp0;
                     }
                 }
                 if (r < TY && gy < g.ny) {
-                    // E_y at (x-1/2, y, z-1/2); p = z, q = x: X on z-faces (slot 6 of z),
-                    // Y on x-faces (slot 5 of x)
+                    // E_y at (x-1/2, y, z-1/2); p = z, q = x: X on z-faces, Y on x-faces
                     const int xm = wrap_once(wx - 1, g.nx);
                     const unsigned int c = at(wx, wy, zz), cx = at(xm, wy, zz);
                     const int mc = m < NA ? m : 0;
                     R Ym = cy5[mc], Rm0 = cry0[mc], Rmm = cryx[mc], fqm = cy0[mc];  // plane zl - 1
                     if (first || m >= NC) {
                         const unsigned int cz = at(wx, wy, zm), cxz = at(xm, wy, zm);
-                        Ym = ldT(Fb[5], cz); Rm0 = ldT(Ry, cz);
-                        Rmm = ldT(Ry, cxz); fqm = ldT(Fb[0], cz);
+                        Ym = ldT(Fb[FX_EY], cz); Rm0 = ldT(Ry, cz);
+                        Rmm = ldT(Ry, cxz); fqm = ldT(Fb[FX_MASS], cz);
                     }
-                    const R Y0 = ldT(Fb[5], c), R00 = ldT(Ry, c), R0m = ldT(Ry, cx), fq0 = ldT(Fb[0], c);
-                    sEy[slot][r][cc] = gs_edge(ldT(Fb[20], c), ldT(Fb[20], cx), Y0, Ym, R00, Rm0, R0m, Rmm,
-                                               ldT(Fb[14], c), ldT(Fb[14], cx), fq0, fqm);
+                    const R Y0 = ldT(Fb[FX_EY], c), R00 = ldT(Ry, c), R0m = ldT(Ry, cx), fq0 = ldT(Fb[FX_MASS], c);
+                    sEy[slot][r][cc] = gs_edge(ldT(Fb[FZ_EY], c), ldT(Fb[FZ_EY], cx), Y0, Ym, R00, Rm0, R0m, Rmm,
+                                               ldT(Fb[FZ_MASS], c), ldT(Fb[FZ_MASS], cx), fq0, fqm);
                     if (m < NC) {
                         cy5[mc] = Y0; cry0[mc] = R00; cryx[mc] = R0m; cy0[mc] = fq0;
                     }
@@ -490,14 +641,9 @@ struct CtTile {
         double vmin = INFINITY;
         int lv = 0;
         fill_level(lv ^ 1, k0, true);  // level k0 - 1/2
-        // z fluxes on the low face of the current plane (the high face of the plane below)
-        R fzc[5];
-    #pragma unroll
-        for (int v = 0; v < 5; ++v) fzc[v] = live && ZC ? ldT(Fb[14 + v], at(i, j, k0)) : R(0);
         R b3c = R(0);  // CFL: the updated B_z on the low face, from the plane below
         bool have_b3 = false;
-        const double bdt = a.co.bdt, g0 = a.co.g0, g1 = a.co.g1;
-        const R bdtr = R(bdt), g0r = R(g0), g1r = R(g1);
+        const R bdtr = R(a.co.bdt), g0r = R(a.co.g0), g1r = R(a.co.g1);
         const R idx = R(g.inv_dx[0]), idy = R(g.inv_dx[1]), idz = R(g.inv_dx[2]);
 
         for (int k = k0; k < k1; ++k) {
@@ -513,51 +659,10 @@ struct CtTile {
             __syncthreads();
 
             if (live) {
+    #pragma clang fp contract(off)
                 const int ip = i + 1 == g.nx ? 0 : i + 1, jp = j + 1 == g.ny ? 0 : j + 1;
                 const int kp = k + 1 == g.nz ? 0 : k + 1;
                 const unsigned int c = at(i, j, k), cx = at(ip, j, k), cy = at(i, jp, k), cz = at(i, j, kp);
-                // flux divergence: density and momenta in R, energy in FP64
-                R L[4];
-    #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const R fzh = ldT(Fb[14 + v], cz);
-                    if (!ZC) fzc[v] = ldT(Fb[14 + v], c);
-                    const R fx = (ldT(Fb[v], cx) - ldT(Fb[v], c)) * idx;
-                    const R fy = (ldT(Fb[7 + v], cy) - ldT(Fb[7 + v], c)) * idy;
-                    const R fz = (fzh - fzc[v]) * idz;
-                    L[v] = -((fx + fy) + fz);
-                    fzc[v] = fzh;
-                }
-                double LE;
-                {
-                    const R fzh = ldT(Fb[18], cz);
-                    if (!ZC) fzc[4] = ldT(Fb[18], c);
-                    const double fx = ((double)ldT(Fb[4], cx) - (double)ldT(Fb[4], c)) * g.inv_dx[0];
-                    const double fy = ((double)ldT(Fb[11], cy) - (double)ldT(Fb[11], c)) * g.inv_dx[1];
-                    const double fz = ((double)fzh - (double)fzc[4]) * g.inv_dx[2];
-                    LE = -((fx + fy) + fz);
-                    fzc[4] = fzh;
-                }
-                R o[4];
-                double oE;
-                if (IN) {
-                    const R rho_in = ldT(a.in.rho, c);
-                    const R m_in[3] = {ldT(a.in.m[0], c), ldT(a.in.m[1], c), ldT(a.in.m[2], c)};
-                    L[1] += rho_in * R(P.gacc[0]);
-                    L[2] += rho_in * R(P.gacc[1]);
-                    L[3] += rho_in * R(P.gacc[2]);
-                    LE += ((double)m_in[0] * P.gacc[0] + (double)m_in[1] * P.gacc[1]) + (double)m_in[2] * P.gacc[2];
-                    o[0] = (g0r * rho_in + g1r * ldT(a.base.rho, c)) + bdtr * L[0];
-    #pragma unroll
-                    for (int v = 0; v < 3; ++v) o[1 + v] = (g0r * m_in[v] + g1r * ldT(a.base.m[v], c)) + bdtr * L[1 + v];
-                    oE = (g0 * ldT(a.in.E, c) + g1 * ldT(a.base.E, c)) + bdt * LE;
-                } else {
-                    o[0] = g1r * ldT(a.base.rho, c) + bdtr * L[0];
-    #pragma unroll
-                    for (int v = 0; v < 3; ++v) o[1 + v] = g1r * ldT(a.base.m[v], c) + bdtr * L[1 + v];
-                    oE = g1 * ldT(a.base.E, c) + bdt * LE;
-                }
-
                 // faces of this cell: b1 at x_{i-1/2}, b2 at y_{j-1/2}, b3 at z_{k-1/2}
                 const int ol = lv ^ 1, nl = lv;
                 auto comb = [&](int comp, unsigned int cc, R lb) -> R {
@@ -587,13 +692,14 @@ struct CtTile {
                     const double bx = 0.5 * ((double)b1 + (double)nb1(lane + 1, cx));
                     const double by = 0.5 * ((double)b2 + (double)nb2(row + 1, cy));
                     const double bz = 0.5 * ((double)b3 + (double)b3c);
-                    double d = o[0];
+                    double d = ldT(a.out.rho, c);
                     if (d < P.rho_floor) d = P.rho_floor;
                     const double id = rcp(d);
-                    const double v[3] = {(double)o[1] * id, (double)o[2] * id, (double)o[3] * id};
+                    const double v[3] = {(double)ldT(a.out.m[0], c) * id, (double)ldT(a.out.m[1], c) * id,
+                                         (double)ldT(a.out.m[2], c) * id};
                     const double ke = 0.5 * d * ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
                     const double b2s = (bx * bx + by * by) + bz * bz;
-                    double pr = (P.gamma - 1.0) * ((oE - ke) - 0.5 * b2s);
+                    double pr = (P.gamma - 1.0) * ((ldT(a.out.E, c) - ke) - 0.5 * b2s);
                     if (pr < P.p_floor) pr = P.p_floor;
                     const double bd[3] = {bx, by, bz};
     #pragma unroll
@@ -603,10 +709,6 @@ struct CtTile {
                     }
                 }
                 // out never aliases in or base (the host rotates three registers)
-                stT(a.out.rho, c, o[0]);
-    #pragma unroll
-                for (int v = 0; v < 3; ++v) stT(a.out.m[v], c, o[1 + v]);
-                stT(a.out.E, c, oE);
                 stT(a.out.b[0], c, b1);
                 stT(a.out.b[1], c, b2);
                 stT(a.out.b[2], c, b3);

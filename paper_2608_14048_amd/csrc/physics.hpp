@@ -206,14 +206,32 @@ __device__ __forceinline__ void face_states(const R* s, R& aL, R& aR)
 // adiabatic MHD in the face frame
 // ----------------------------------------------------------------------------------
 
+// a1 b1 + a2 b2 over the two transverse components, rounded as written (no FMA): the
+// sum of two rounded products does not depend on which transverse direction is called
+// t1, so an x face and a y face that are images of each other under the swap of x and
+// y (their transverse pairs come in opposite orders) give the same bits.
+template <class R>
+__device__ __forceinline__ R tsum(R a1, R b1, R a2, R b2)
+{
+#pragma clang fp contract(off)
+    return a1 * b1 + a2 * b2;
+}
+
+// The Riemann solvers below round every operation as written: each product that is
+// fused into an add is an explicit fma_r, nothing is left to the compiler's
+// contraction.  A face then gives the same bits wherever the solver is inlined (the
+// cell's own faces, the tile's high faces, the z face that opens a chunk), so results
+// do not depend on how the grid is tiled or split into z chunks.
+
 // Fast magnetosonic speed along a direction with field component bd; b2 = |B|^2.
 template <class R>
 __device__ __forceinline__ R fast_speed(R gam, R d, R p, R b2, R bd)
 {
+#pragma clang fp contract(off)
     const R id = rcp(d);
     const R a2 = gam * p * id;
-    const R s = a2 + b2 * id;
-    const R disc = max_r(s * s - R(4) * a2 * (bd * bd) * id, R(0));
+    const R s = fma_r(b2, id, a2);
+    const R disc = max_r(fma_r(s, s, -(R(4) * a2 * (bd * bd) * id)), R(0));
     return sqrt_r(R(0.5) * (s + sqrt_r(disc)));
 }
 
@@ -225,33 +243,58 @@ struct Side {
     R pt, vb, cf;
 };
 
+// What the HLLD wave speeds and star states need of one face-frame state: total
+// pressure, v.B, total energy and the fast speed (the conserved vector and the flux are
+// built later for the one side the face's region needs).
+template <class R>
+struct Lite {
+    R pt, vb, e, cf;
+};
+
+template <class R>
+__device__ __forceinline__ void lite_of(const Prim7<R>& w, R bn, R gam, R gm1inv, Lite<R>& s)
+{
+#pragma clang fp contract(off)
+    const R bt2 = tsum(w.bt1, w.bt1, w.bt2, w.bt2);
+    const R b2 = fma_r(bn, bn, bt2);
+    const R v2 = fma_r(w.vn, w.vn, tsum(w.vt1, w.vt1, w.vt2, w.vt2));
+    s.pt = fma_r(R(0.5), b2, w.p);
+    s.e = fma_r(w.p, gm1inv, fma_r(R(0.5) * w.d, v2, R(0.5) * b2));
+    s.vb = fma_r(w.vn, bn, tsum(w.vt1, w.bt1, w.vt2, w.bt2));
+    s.cf = fast_speed(gam, w.d, w.p, b2, bn);
+}
+
+// Conserved vector and physical flux of one state.
+template <class R>
+__device__ __forceinline__ void uf_of(const Prim7<R>& w, const Lite<R>& s, R bn, R U[7], R F[7])
+{
+#pragma clang fp contract(off)
+    const R mn = w.d * w.vn;
+    U[0] = w.d;
+    U[1] = mn;
+    U[2] = w.d * w.vt1;
+    U[3] = w.d * w.vt2;
+    U[4] = s.e;
+    U[5] = w.bt1;
+    U[6] = w.bt2;
+    F[0] = mn;
+    F[1] = fma_r(-bn, bn, fma_r(mn, w.vn, s.pt));
+    F[2] = fma_r(mn, w.vt1, -(bn * w.bt1));
+    F[3] = fma_r(mn, w.vt2, -(bn * w.bt2));
+    F[4] = fma_r(s.e + s.pt, w.vn, -(bn * s.vb));
+    F[5] = fma_r(w.bt1, w.vn, -(bn * w.vt1));
+    F[6] = fma_r(w.bt2, w.vn, -(bn * w.vt2));
+}
+
 template <class R>
 __device__ __forceinline__ void side_of(const Prim7<R>& w, R bn, R gam, R gm1inv, Side<R>& s)
 {
-    const R bt2 = w.bt1 * w.bt1 + w.bt2 * w.bt2;
-    const R b2 = bn * bn + bt2;
-    const R v2 = w.vn * w.vn + (w.vt1 * w.vt1 + w.vt2 * w.vt2);
-    const R pt = w.p + R(0.5) * b2;
-    const R E = w.p * gm1inv + R(0.5) * w.d * v2 + R(0.5) * b2;
-    const R vb = w.vn * bn + (w.vt1 * w.bt1 + w.vt2 * w.bt2);
-    const R mn = w.d * w.vn;
-    s.U[0] = w.d;
-    s.U[1] = mn;
-    s.U[2] = w.d * w.vt1;
-    s.U[3] = w.d * w.vt2;
-    s.U[4] = E;
-    s.U[5] = w.bt1;
-    s.U[6] = w.bt2;
-    s.F[0] = mn;
-    s.F[1] = mn * w.vn + pt - bn * bn;
-    s.F[2] = mn * w.vt1 - bn * w.bt1;
-    s.F[3] = mn * w.vt2 - bn * w.bt2;
-    s.F[4] = (E + pt) * w.vn - bn * vb;
-    s.F[5] = w.bt1 * w.vn - bn * w.vt1;
-    s.F[6] = w.bt2 * w.vn - bn * w.vt2;
-    s.pt = pt;
-    s.vb = vb;
-    s.cf = fast_speed(gam, w.d, w.p, b2, bn);
+    Lite<R> l;
+    lite_of(w, bn, gam, gm1inv, l);
+    uf_of(w, l, bn, s.U, s.F);
+    s.pt = l.pt;
+    s.vb = l.vb;
+    s.cf = l.cf;
 }
 
 template <class R>
@@ -265,6 +308,7 @@ template <class R>
 __device__ __forceinline__ void riemann_hlle(const Prim7<R>& L, const Prim7<R>& Rt, R bn, R gam,
                                              R gm1inv, Flux7<R>& f)
 {
+#pragma clang fp contract(off)
     Side<R> a, b;
     side_of(L, bn, gam, gm1inv, a);
     side_of(Rt, bn, gam, gm1inv, b);
@@ -273,51 +317,11 @@ __device__ __forceinline__ void riemann_hlle(const Prim7<R>& L, const Prim7<R>& 
     const R sr = max_r(L.vn, Rt.vn) + cmax;
     const R bm = min_r(sl, R(0)), bp = max_r(sr, R(0));
     const R inv = rcp(bp - bm);
+    const R bpm = bp * bm;
     R o[7];
 #pragma unroll
-    for (int q = 0; q < 7; ++q) o[q] = (bp * a.F[q] - bm * b.F[q] + bp * bm * (b.U[q] - a.U[q])) * inv;
+    for (int q = 0; q < 7; ++q) o[q] = fma_r(bpm, b.U[q] - a.U[q], fma_r(bp, a.F[q], -(bm * b.F[q]))) * inv;
     to_flux(o, f);
-}
-
-// What the HLLD wave speeds and star states need of one face-frame state: total
-// pressure, v.B, total energy and the fast speed (the conserved vector and the flux are
-// built later for the one side the face's region needs).
-template <class R>
-struct Lite {
-    R pt, vb, e, cf;
-};
-
-template <class R>
-__device__ __forceinline__ void lite_of(const Prim7<R>& w, R bn, R gam, R gm1inv, Lite<R>& s)
-{
-    const R bt2 = w.bt1 * w.bt1 + w.bt2 * w.bt2;
-    const R b2 = bn * bn + bt2;
-    const R v2 = w.vn * w.vn + (w.vt1 * w.vt1 + w.vt2 * w.vt2);
-    s.pt = w.p + R(0.5) * b2;
-    s.e = w.p * gm1inv + R(0.5) * w.d * v2 + R(0.5) * b2;
-    s.vb = w.vn * bn + (w.vt1 * w.bt1 + w.vt2 * w.bt2);
-    s.cf = fast_speed(gam, w.d, w.p, b2, bn);
-}
-
-// Conserved vector and physical flux of one state (the formulas of side_of).
-template <class R>
-__device__ __forceinline__ void uf_of(const Prim7<R>& w, const Lite<R>& s, R bn, R U[7], R F[7])
-{
-    const R mn = w.d * w.vn;
-    U[0] = w.d;
-    U[1] = mn;
-    U[2] = w.d * w.vt1;
-    U[3] = w.d * w.vt2;
-    U[4] = s.e;
-    U[5] = w.bt1;
-    U[6] = w.bt2;
-    F[0] = mn;
-    F[1] = mn * w.vn + s.pt - bn * bn;
-    F[2] = mn * w.vt1 - bn * w.bt1;
-    F[3] = mn * w.vt2 - bn * w.bt2;
-    F[4] = (s.e + s.pt) * w.vn - bn * s.vb;
-    F[5] = w.bt1 * w.vn - bn * w.vt1;
-    F[6] = w.bt2 * w.vn - bn * w.vt2;
 }
 
 // One side of the HLLD star region: density behind the fast wave, transverse velocity
@@ -332,23 +336,27 @@ template <class R>
 __device__ __forceinline__ void star_of(const Prim7<R>& w, const Lite<R>& s, R bn, R S, R SM, R pts,
                                         R eps, Star<R>& o)
 {
+#pragma clang fp contract(off)
     const R du = S - w.vn;
-    const R ds = rcp(S - SM);
-    o.d = w.d * du * ds;
-    const R den = w.d * du * (S - SM) - bn * bn;
+    const R dsm = S - SM;
+    const R ds = rcp(dsm);
+    const R mdu = w.d * du;
+    o.d = mdu * ds;
+    const R bn2 = bn * bn;
+    const R den = fma_r(mdu, dsm, -bn2);
     if (abs_r(den) <= eps * pts) {
         o.vt1 = w.vt1; o.vt2 = w.vt2; o.bt1 = w.bt1; o.bt2 = w.bt2;
     } else {
         const R r = rcp(den);
         const R cv = bn * (SM - w.vn) * r;
-        const R cb = (w.d * du * du - bn * bn) * r;
-        o.vt1 = w.vt1 - w.bt1 * cv;
-        o.vt2 = w.vt2 - w.bt2 * cv;
+        const R cb = fma_r(mdu, du, -bn2) * r;
+        o.vt1 = fma_r(-w.bt1, cv, w.vt1);
+        o.vt2 = fma_r(-w.bt2, cv, w.vt2);
         o.bt1 = w.bt1 * cb;
         o.bt2 = w.bt2 * cb;
     }
-    o.vb = SM * bn + (o.vt1 * o.bt1 + o.vt2 * o.bt2);
-    o.e = (du * s.e - s.pt * w.vn + pts * SM + bn * (s.vb - o.vb)) * ds;
+    o.vb = fma_r(SM, bn, tsum(o.vt1, o.bt1, o.vt2, o.bt2));
+    o.e = fma_r(du, s.e, fma_r(-s.pt, w.vn, fma_r(pts, SM, bn * (s.vb - o.vb)))) * ds;
     o.sqd = sqrt_r(o.d);
 }
 
@@ -361,6 +369,7 @@ template <class R>
 __device__ __forceinline__ void riemann_hlld(const Prim7<R>& L, const Prim7<R>& Rt, R bn, R gam,
                                              R gm1inv, R eps, Flux7<R>& f)
 {
+#pragma clang fp contract(off)
     Lite<R> a, b;
     lite_of(L, bn, gam, gm1inv, a);
     lite_of(Rt, bn, gam, gm1inv, b);
@@ -377,8 +386,8 @@ __device__ __forceinline__ void riemann_hlld(const Prim7<R>& L, const Prim7<R>& 
     if (!sup) {
         const R ml = L.d * (sl - L.vn), mr = Rt.d * (sr - Rt.vn);  // mass fluxes into the fan
         const R iden = rcp(mr - ml);
-        const R SM = (mr * Rt.vn - ml * L.vn - b.pt + a.pt) * iden;
-        const R pts = (mr * a.pt - ml * b.pt + ml * mr * (Rt.vn - L.vn)) * iden;
+        const R SM = (fma_r(mr, Rt.vn, -(ml * L.vn)) - b.pt + a.pt) * iden;
+        const R pts = fma_r(ml * mr, Rt.vn - L.vn, fma_r(mr, a.pt, -(ml * b.pt))) * iden;
 
         Star<R> x, y;
         star_of(L, a, bn, sl, SM, pts, eps, x);
@@ -402,12 +411,13 @@ __device__ __forceinline__ void riemann_hlld(const Prim7<R>& L, const Prim7<R>& 
             } else {
                 const R sg = bn > R(0) ? R(1) : R(-1);
                 const R inv = rcp(x.sqd + y.sqd);
-                const R v1 = (x.sqd * x.vt1 + y.sqd * y.vt1 + (y.bt1 - x.bt1) * sg) * inv;
-                const R v2 = (x.sqd * x.vt2 + y.sqd * y.vt2 + (y.bt2 - x.bt2) * sg) * inv;
-                const R b1 = (x.sqd * y.bt1 + y.sqd * x.bt1 + x.sqd * y.sqd * (y.vt1 - x.vt1) * sg) * inv;
-                const R b2 = (x.sqd * y.bt2 + y.sqd * x.bt2 + x.sqd * y.sqd * (y.vt2 - x.vt2) * sg) * inv;
-                const R vbss = SM * bn + (v1 * b1 + v2 * b2);
-                const R ess = left ? x.e - x.sqd * (x.vb - vbss) * sg : y.e + y.sqd * (y.vb - vbss) * sg;
+                const R xy = x.sqd * y.sqd;
+                const R v1 = fma_r(x.sqd, x.vt1, fma_r(y.sqd, y.vt1, (y.bt1 - x.bt1) * sg)) * inv;
+                const R v2 = fma_r(x.sqd, x.vt2, fma_r(y.sqd, y.vt2, (y.bt2 - x.bt2) * sg)) * inv;
+                const R b1 = fma_r(x.sqd, y.bt1, fma_r(y.sqd, x.bt1, xy * (y.vt1 - x.vt1) * sg)) * inv;
+                const R b2 = fma_r(x.sqd, y.bt2, fma_r(y.sqd, x.bt2, xy * (y.vt2 - x.vt2) * sg)) * inv;
+                const R vbss = fma_r(SM, bn, tsum(v1, b1, v2, b2));
+                const R ess = left ? fma_r(-x.sqd * sg, x.vb - vbss, x.e) : fma_r(y.sqd * sg, y.vb - vbss, y.e);
                 ub[0] = st.d; ub[1] = st.d * SM; ub[2] = st.d * v1; ub[3] = st.d * v2;
                 ub[4] = ess; ub[5] = b1; ub[6] = b2;
             }
@@ -428,7 +438,7 @@ __device__ __forceinline__ void riemann_hlld(const Prim7<R>& L, const Prim7<R>& 
     }
     R o[7];
 #pragma unroll
-    for (int q = 0; q < 7; ++q) o[q] = F[q] + S * (ua[q] - U[q]) + Sa * (ub[q] - ua[q]);
+    for (int q = 0; q < 7; ++q) o[q] = fma_r(Sa, ub[q] - ua[q], fma_r(S, ua[q] - U[q], F[q]));
     to_flux(o, f);
 }
 
@@ -439,6 +449,7 @@ __device__ __forceinline__ void riemann_hlld(const Prim7<R>& L, const Prim7<R>& 
 template <class R>
 __device__ __forceinline__ void riemann_iso_hlle(const Prim4<R>& L, const Prim4<R>& Rt, R cs, Flux4<R>& f)
 {
+#pragma clang fp contract(off)
     const R sl = min_r(L.vn, Rt.vn) - cs, sr = max_r(L.vn, Rt.vn) + cs;
     const R bm = min_r(sl, R(0)), bp = max_r(sr, R(0));
     const R inv = rcp(bp - bm);
@@ -446,11 +457,12 @@ __device__ __forceinline__ void riemann_iso_hlle(const Prim4<R>& L, const Prim4<
     const R mL = L.d * L.vn, mR = Rt.d * Rt.vn;
     const R UL[4] = {L.d, mL, L.d * L.vt1, L.d * L.vt2};
     const R UR[4] = {Rt.d, mR, Rt.d * Rt.vt1, Rt.d * Rt.vt2};
-    const R FL[4] = {mL, mL * L.vn + c2 * L.d, mL * L.vt1, mL * L.vt2};
-    const R FR[4] = {mR, mR * Rt.vn + c2 * Rt.d, mR * Rt.vt1, mR * Rt.vt2};
+    const R FL[4] = {mL, fma_r(mL, L.vn, c2 * L.d), mL * L.vt1, mL * L.vt2};
+    const R FR[4] = {mR, fma_r(mR, Rt.vn, c2 * Rt.d), mR * Rt.vt1, mR * Rt.vt2};
+    const R bpm = bp * bm;
     R o[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) o[q] = (bp * FL[q] - bm * FR[q] + bp * bm * (UR[q] - UL[q])) * inv;
+    for (int q = 0; q < 4; ++q) o[q] = fma_r(bpm, UR[q] - UL[q], fma_r(bp, FL[q], -(bm * FR[q]))) * inv;
     f.d = o[0]; f.mn = o[1]; f.mt1 = o[2]; f.mt2 = o[3];
 }
 
@@ -458,12 +470,14 @@ __device__ __forceinline__ void riemann_iso_hlle(const Prim4<R>& L, const Prim4<
 template <class R>
 __device__ __forceinline__ void riemann_dust(const Prim4<R>& L, const Prim4<R>& Rt, Flux4<R>& f)
 {
+#pragma clang fp contract(off)
     const R a = max_r(abs_r(L.vn), abs_r(Rt.vn));
     const R UL[4] = {L.d, L.d * L.vn, L.d * L.vt1, L.d * L.vt2};
     const R UR[4] = {Rt.d, Rt.d * Rt.vn, Rt.d * Rt.vt1, Rt.d * Rt.vt2};
+    const R ha = R(0.5) * a;
     R o[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) o[q] = R(0.5) * (L.vn * UL[q] + Rt.vn * UR[q]) - R(0.5) * a * (UR[q] - UL[q]);
+    for (int q = 0; q < 4; ++q) o[q] = fma_r(-ha, UR[q] - UL[q], R(0.5) * fma_r(L.vn, UL[q], Rt.vn * UR[q]));
     f.d = o[0]; f.mn = o[1]; f.mt1 = o[2]; f.mt2 = o[3];
 }
 

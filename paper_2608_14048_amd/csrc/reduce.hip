@@ -44,9 +44,12 @@ __device__ __forceinline__ double block_min(double v)
     return r;
 }
 
+// The same arithmetic, rounded as written, as the time step the last stage of a step
+// reduces (mhd_tiles.hpp), so a state gives the same bits whichever kernel takes its step.
 __global__ __launch_bounds__(kBlock) void k_cfl_mhd(Geo g, MhdParams p, const double* __restrict__ U,
                                                     double* __restrict__ partial)
 {
+#pragma clang fp contract(off)
     const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
     double r = INFINITY;
     if (c < g.n) {
@@ -58,7 +61,8 @@ __global__ __launch_bounds__(kBlock) void k_cfl_mhd(Geo g, MhdParams p, const do
         const double bz = 0.5 * (U[7 * n + c] + U[7 * n + shifted(g, i, j, k, 2, 1)]);
         double d = U[c];
         if (d < p.rho_floor) d = p.rho_floor;
-        const double v[3] = {U[n + c] / d, U[2 * n + c] / d, U[3 * n + c] / d};
+        const double id = rcp(d);
+        const double v[3] = {U[n + c] * id, U[2 * n + c] * id, U[3 * n + c] * id};
         const double ke = 0.5 * d * ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
         const double b2 = (bx * bx + by * by) + bz * bz;
         double pr = (p.gamma - 1.0) * ((U[4 * n + c] - ke) - 0.5 * b2);
@@ -67,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void k_cfl_mhd(Geo g, MhdParams p, const do
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const double cf = fast_speed(p.gamma, d, pr, b2, bd[a]);
-            r = min_nan(r, g.dx[a] / (fabs(v[a]) + cf));
+            r = min_nan(r, div_r(g.dx[a], fabs(v[a]) + cf));
         }
     }
     r = block_min(r);

@@ -215,3 +215,75 @@ def test_zero_network_is_the_plain_step_and_training_lowers_the_loss():
         a.close()
         b.close()
         cl.close()
+
+
+def test_closure_step_falls_back_to_the_plain_step():
+    """A network scaled so that its corrections would drive the state below the floors
+    (or make it non-finite) is rejected: the plain step stands, bit for bit, and the
+    step reports the fallback; a zero network is applied (and changes nothing)."""
+    shape = (16, 16, 16)
+    st = I.turbulence_block(shape, seed=11)[0]
+    scheme = dict(recon="ppm", riemann="hlld", integ="vl2")
+    a, b = B.Sim(shape, scheme=scheme), B.Sim(shape, scheme=scheme)
+    cl = B.Closure(shape)
+    try:
+        a.set_state(st)
+        b.set_state(st)
+        dt = a.dt_cfl()
+        a.step(dt)
+        assert cl.step(b, dt, report=True) == 1          # zero network: applied
+        assert np.array_equal(a.state(), b.state())
+        assert a.dt_cfl() == b.dt_cfl()
+        # a wild network: corrections of order 1e6 of the state
+        rng = np.random.default_rng(12)
+        cl.set_params(C.pack(random_params(rng, scale=(2.0, 2.0, 2.0, 2.0))).astype(np.float32))
+        mu = C.primitives(st, shape).reshape(8, -1).mean(axis=1)
+        sd = C.primitives(st, shape).reshape(8, -1).std(axis=1) + 1e-3
+        cl.set_scales(mu, sd, np.full(5, 1e3), 1e3, np.ones(5), 1.0)
+        a.set_state(st)
+        b.set_state(st)
+        a.step(dt)
+        assert cl.step(b, dt, report=True) == 0          # rejected: the plain step stands
+        assert np.array_equal(a.state(), b.state())
+        assert a.dt_cfl() == b.dt_cfl()
+        # a mild network with small output scales is applied and changes the state
+        cl.set_params(C.pack(random_params(rng, scale=(0.2, 0.1, 0.1, 0.1))).astype(np.float32))
+        cl.set_scales(mu, sd, np.full(5, 1e-4), 1e-4, np.ones(5), 1.0)
+        b.set_state(st)
+        assert cl.step(b, dt, report=True) == 1
+        d = np.abs(b.state() - a.state()).max()
+        assert 0.0 < d < 1e-3, d
+    finally:
+        a.close()
+        b.close()
+        cl.close()
+
+
+def test_closure_step_rejects_other_grids_and_streams():
+    shape = (16, 16, 8)
+    cl = B.Closure(shape)
+    try:
+        # the same number of cells on a transposed grid
+        other = B.Sim((16, 8, 16), scheme=dict(recon="plm"))
+        other.set_state(I.turbulence_block((16, 8, 16), seed=1)[0])
+        with pytest.raises(B.MhdError) as e:
+            cl.step(other, 1e-3)
+        assert e.value.code == -1
+        other.close()
+        # the same grid on another stream
+        s = torch.cuda.Stream()
+        sim = B.Sim(shape, scheme=dict(recon="plm"), stream=s)
+        sim.set_state(I.turbulence_block(shape, seed=2)[0])
+        with pytest.raises(B.MhdError) as e:
+            cl.step(sim, 1e-3)
+        assert e.value.code == -1
+        sim.close()
+        # an FP32-bulk context
+        sim = B.Sim(shape, scheme=dict(recon="plm", prec="fp32_bulk"))
+        sim.set_state(I.turbulence_block(shape, seed=2)[0])
+        with pytest.raises(B.MhdError) as e:
+            cl.step(sim, 1e-3)
+        assert e.value.code == -2
+        sim.close()
+    finally:
+        cl.close()

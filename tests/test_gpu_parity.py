@@ -8,6 +8,7 @@ not divided by themselves.  The GPU contracts a*b+c into FMAs and multiplies by
 reciprocals where the oracle divides; both round differently at the last bit only.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -35,13 +36,14 @@ class Pair:
 
     def __init__(self, shape, length=(1.0, 1.0, 1.0), eos="adiabatic_mhd", gamma=5.0 / 3.0,
                  tstop=(), gacc=(0.0, 0.0, 0.0), recon="plm", riemann="hlld", integ="vl2",
-                 courant=0.3):
+                 courant=0.3, floors=None):
         self.shape, self.eos, self.gamma, self.nd = tuple(shape), eos, gamma, len(tstop)
+        fl = dict(floors or {})
         self.cfg = oracle.make_cfg(shape, length=length, eos=eos, gamma=gamma, tstop=tstop,
                                    gacc=gacc, recon=recon, riemann=riemann, integ=integ,
-                                   courant=courant)
+                                   courant=courant, **fl)
         self.sim = B.Sim(shape, length, physics=dict(eos=eos, gamma=gamma, tstop=tuple(tstop),
-                                                     gacc=gacc),
+                                                     gacc=gacc, **fl),
                          scheme=dict(recon=recon, riemann=riemann, integ=integ, courant=courant))
 
     def close(self):
@@ -269,26 +271,53 @@ def test_linear_wave_32_hundred_steps():
         pr.close()
 
 
-# Decaying turbulence is chaotic: two FP64 evaluations that differ in the last bit (FMA
-# contraction, reciprocal products) separate exponentially, fastest where a limiter or
-# a Riemann-fan branch flips.  Measured max-norm class errors after 100 steps: 64^3
-# seeds 1-3 7e-11 .. 9e-10, 128^3 seed 1 1e-8, while one step stays below 1e-14.  The
-# 100-step bound is therefore taken in the relative L1 norm of each conserved class
-# for turbulence (the max norm in the smooth wave test above), with the max norm
-# reported and held to a loose bound that a real defect would exceed by far.
-TURB_MAX_TOL = 1e-8
+# Decaying turbulence is chaotic: two FP64 evaluations that differ in the last bit
+# separate, fastest where a limiter or a Riemann-fan branch flips.  How far the oracle
+# separates from itself is recorded in tests/golden/turbulence_sensitivity.txt (written
+# by make_turbulence_sensitivity.py from the oracle alone): for seeds 1-3 at 64^3, with
+# the input moved by one ulp, or every value moved by one ulp after every step, the
+# per-class max-norm separation stays below 1e-11 for the first 30 steps and reaches
+# 1e-10 .. 1e-9 by step 100.  The GPU is held to the 1e-10 contract while the oracle's
+# own separation stays below 1e-11, and after that to TURB_SEP_MULT times the largest
+# separation the record shows up to that step; relative L1 stays within 1e-10 throughout.
+TURB_SEP_MULT = 3.0
+
+
+def _sensitivity_envelope():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "turbulence_sensitivity.txt")
+    rec = np.loadtxt(path)
+    steps = int(rec[:, 1].max())
+    env = np.zeros(steps + 1)
+    for k in range(1, steps + 1):
+        env[k] = rec[rec[:, 1] <= k][:, 2:].max()
+    return env
 
 
 def test_turbulence_64_hundred_steps():
-    """Decaying turbulence recipe at 64^3, VL2 + PPM + HLLD + CT, 100 steps."""
+    """Decaying turbulence recipe at 64^3, VL2 + PPM + HLLD + CT, 100 steps, compared
+    with the oracle after every step."""
+    env = _sensitivity_envelope()
     st = I.turbulence(64, seed=1)
     pr = Pair((64, 64, 64), recon="ppm", riemann="hlld", integ="vl2")
     try:
-        ref, got = run_both(pr, st, 100)
-        e1 = l1_rel(pr, got, ref)
+        s = st.copy()
+        pr.sim.set_state(st)
+        worst = []
+        for k in range(1, 101):
+            dt = oracle.dt_cfl(pr.cfg, s)
+            s = oracle.step(pr.cfg, s, dt)
+            pr.sim.step(dt)
+            got = pr.sim.state()
+            e = max(class_errors(pr, got, s).values())
+            worst.append(e)
+            bound = RUN_TOL if env[k] < 1e-11 else max(RUN_TOL, TURB_SEP_MULT * env[k])
+            assert e <= bound, (k, e, bound, env[k])
+        e1 = l1_rel(pr, got, s)
+        _say(f"  turb64 x100: max-norm class error at steps 10/30/50/100: "
+             f"{worst[9]:.2e} {worst[29]:.2e} {worst[49]:.2e} {worst[99]:.2e}; "
+             f"oracle self-separation envelope {env[10]:.2e} {env[30]:.2e} {env[50]:.2e} {env[100]:.2e}")
         _say(f"  turb64 x100: relative L1 {e1}")
         assert max(e1.values()) <= RUN_TOL, e1
-        assert_close(pr, got, ref, TURB_MAX_TOL, "turb64 x100 (max norm)")
     finally:
         pr.close()
 
@@ -567,12 +596,13 @@ def dust_l1_rel(pair, got, ref):
 
 
 class PairDust32(Pair):
-    def __init__(self, shape, tstop, gacc=(0.05, 0.0, 0.0), recon="plm"):
+    def __init__(self, shape, tstop, gacc=(0.05, 0.0, 0.0), recon="plm", floors=None):
         super().__init__(shape, eos="isothermal_hydro", tstop=tstop, gacc=gacc, recon=recon,
-                         riemann="hlle", integ="imex2p")
+                         riemann="hlle", integ="imex2p", floors=floors)
         self.sim.close()
         self.sim = B.Sim(shape, (1.0, 1.0, 1.0),
-                         physics=dict(eos="isothermal_hydro", tstop=tuple(tstop), gacc=gacc),
+                         physics=dict(eos="isothermal_hydro", tstop=tuple(tstop), gacc=gacc,
+                                      **dict(floors or {})),
                          scheme=dict(recon=recon, riemann="hlle", integ="imex2p", courant=0.3,
                                      prec="fp32_bulk"))
 
@@ -647,5 +677,159 @@ def test_fp32_dust_invariants():
         pr.sim.set_state(st)
         pr.sim.run(3)
         assert np.array_equal(a, pr.sim.state())
+    finally:
+        pr.close()
+
+
+# ----------------------------------------------------------------------------------
+# floors, the zero-mass-flux branch of the edge average, transpose symmetry
+# ----------------------------------------------------------------------------------
+
+def test_gas_floors_engaged_parity():
+    """Density and pressure floors set inside the range of a rough state, so that a large
+    share of the cells is floored in every stage and in the time step."""
+    shape = (20, 14, 10)
+    st = random_mhd(shape, 12)
+    fl = dict(rho_floor=0.9, p_floor=0.8)
+    for recon, riemann, integ in (("ppm", "hlld", "vl2"), ("plm", "hlle", "rk2")):
+        pr = Pair(shape, recon=recon, riemann=riemann, integ=integ, floors=fl)
+        try:
+            n = int(np.prod(shape))
+            prim = oracle.mhd_prims(pr.cfg, st).reshape(8, -1)
+            raw = st.reshape(8, -1)[0]
+            _say(f"  floored cells: rho {np.mean(raw < 0.9):.2f}, p {np.mean(prim[4] == 0.8):.2f}")
+            assert np.mean(raw < 0.9) > 0.2 and np.mean(prim[4] == 0.8) > 0.2
+            ref, got = run_both(pr, st, 3)
+            assert_close(pr, got, ref, STEP_TOL, f"floors {recon}-{riemann}-{integ} x3")
+        finally:
+            pr.close()
+
+
+def test_dust_floor_engaged_parity():
+    """Two species below the dust floor in a third of the cells, with momenta (the step
+    resets them to the floor at rest), and stage-1 evacuation below the floor."""
+    shape = (16, 12, 10)
+    st, ts = dust_problem(shape, seed=3, nd=4, noise=1e-2)
+    n = int(np.prod(shape))
+    f = st.reshape(-1, n).copy()
+    floor = 1e-3
+    rng = np.random.default_rng(8)
+    for s in (1, 3):
+        low = rng.random(n) < 0.33
+        f[4 * s][low] = floor * rng.uniform(0.0, 0.99, low.sum())
+        f[4 * s + 1][low] = 0.7 * f[4 * s][low]
+        f[4 * s + 2][low] = -0.4 * f[4 * s][low]
+        # just above the floor and moving fast next door: emptied below it in stage 1
+        near = (~low) & (rng.random(n) < 0.2)
+        f[4 * s][near] = 1.02 * floor
+        f[4 * s + 1][near] = 0.9 * floor * np.sign(rng.normal(size=near.sum()))
+    st = f.ravel()
+    for prec in ("fp64", "fp32"):
+        if prec == "fp64":
+            pr = Pair(shape, eos="isothermal_hydro", tstop=ts, gacc=(0.05, 0, 0), recon="plm",
+                      riemann="hlle", integ="imex2p", floors=dict(dust_rho_floor=floor))
+        else:
+            pr = PairDust32(shape, ts, floors=dict(dust_rho_floor=floor))
+        try:
+            tol = STEP_TOL if prec == "fp64" else FP32_DUST_STEP_TOL
+            ref, got = run_both(pr, st, 3, check_dt=prec == "fp64")
+            assert_close(pr, got, ref, tol, f"dust floor {prec} x3")
+        finally:
+            pr.close()
+
+
+def _x_mirror_state(shape, seed):
+    nx, ny, nz = shape
+    rng = np.random.default_rng(seed)
+    full = (nz, ny, nx)
+
+    def even(a):
+        a[..., nx // 2:] = a[..., : nx // 2][..., ::-1]
+        return a
+
+    vy = even(rng.normal(0.0, 0.5, full))
+    vz = even(rng.normal(0.0, 0.5, full))
+    one, zero = np.ones(full), np.zeros(full)
+    return I.mhd_state(one, zero, vy, vz, 0.6 * one / (2.0 / 3.0), 0.8 * one, zero, zero)
+
+
+def _x_mirror_defect(s, shape):
+    """Largest difference between each field of s and its own x-mirror image (B an axial
+    vector: B_x even, B_y and B_z odd; v_x odd), relative to the field's magnitude."""
+    nx, ny, nz = shape
+    f = s.reshape(8, nz, ny, nx)
+    cell = lambda a: a[..., ::-1]
+    face = lambda a: np.roll(a[..., ::-1], 1, axis=-1)
+    checks = {"rho": (f[0], cell(f[0])), "Mx": (f[1], -cell(f[1])), "My": (f[2], cell(f[2])),
+              "Mz": (f[3], cell(f[3])), "E": (f[4], cell(f[4])), "b1": (f[5], face(f[5])),
+              "b2": (f[6], -cell(f[6])), "b3": (f[7], -cell(f[7]))}
+    scale = max(np.abs(f[q]).max() for q in range(8))
+    return {k: float(np.abs(a - b).max() / scale) for k, (a, b) in checks.items()}
+
+
+@pytest.mark.parametrize("integ,recon", [("euler1", "plm"), ("vl2", "plm")])
+def test_zero_mass_flux_branch_parity(integ, recon):
+    """Every x-face mass flux of the first stage is exactly zero (no v_x, uniform density,
+    pressure and B_x, HLLE), so every E_y and E_z edge takes the zero-mass-flux branch of
+    the Gardiner-Stone average.  The oracle keeps this x-mirror-symmetric state
+    mirror-symmetric in every bit (pinned); the GPU must equal the oracle to the step
+    tolerance and stay mirror-symmetric to round-off.  (Its HLLE flux contracts products
+    into FMAs, whose rounding is not symmetric under the left/right swap of a mirror, so
+    the GPU's symmetry holds to the last bits, not bitwise.)  Either one-sided candidate
+    at zero flux would break both by the size of the candidates' difference."""
+    shape = (32, 12, 8)
+    st = _x_mirror_state(shape, 11)
+    length = (1.0, 12 / 32, 8 / 32)
+    pr = Pair(shape, length=length, recon=recon, riemann="hlle", integ=integ)
+    try:
+        ref, got = run_both(pr, st, 1)
+        assert_close(pr, got, ref, STEP_TOL, f"x mirror {integ}-{recon}")
+        d = _x_mirror_defect(got, shape)
+        _say(f"  mirror defect of the GPU state: {d}")
+        assert max(d.values()) <= 1e-14, d
+        assert max(_x_mirror_defect(ref, shape).values()) == 0.0
+        # the branch matters here: the two candidates differ by O(1e-2) of the field
+        assert np.abs(ref - st).max() > 1e-4
+    finally:
+        pr.close()
+
+
+@pytest.mark.parametrize("recon,riemann,integ", [("ppm", "hlld", "vl2"), ("plm", "hlle", "rk2")])
+def test_bitwise_transpose_symmetry_gpu(recon, riemann, integ):
+    """An x<->y symmetric state stays x<->y symmetric in every bit over 8 GPU steps (the
+    property the paper demonstrates on its implosion test), as the oracle's does."""
+    n, nz = 24, 12
+    rng = np.random.default_rng(4)
+    full = (nz, n, n)
+    T = lambda a: np.swapaxes(a, 1, 2)
+    sym = lambda a: 0.5 * (a + T(a))
+    rho = sym(rng.uniform(0.5, 1.5, full))
+    vx = rng.normal(0, 0.4, full)
+    vy = T(vx)
+    vz = sym(rng.normal(0, 0.4, full))
+    p = sym(rng.uniform(0.5, 1.2, full))
+    dx = (1.0 / n, 1.0 / n, 0.5 / nz)
+    # the curl of a potential with A_y = -T(A_x) and A_z = -T(A_z) has b1 = T(b2) and
+    # b3 = T(b3) (the swap of x and y is a reflection, and B an axial vector)
+    ax = rng.normal(0, 0.02, full)
+    ay = -T(ax)
+    a = rng.normal(0, 0.02, full)
+    az = 0.5 * (a - T(a))
+    b1, b2, b3 = I.faces_from_potential(ax, ay, az, *dx)
+    b1, b2, b3 = b1 + 0.5, b2 + 0.5, b3 - 0.2
+    assert np.array_equal(b1, T(b2)) and np.array_equal(b3, T(b3))
+    st = I.mhd_state(rho, vx, vy, vz, p * 1.5, b1, b2, b3)
+    pr = Pair((n, n, nz), length=(1.0, 1.0, 0.5), recon=recon, riemann=riemann, integ=integ)
+    try:
+        pr.sim.set_state(st)
+        pr.sim.run(8)
+        g = pr.sim.state().reshape(8, nz, n, n)
+        assert np.array_equal(g[0], T(g[0]))
+        assert np.array_equal(g[1], T(g[2]))
+        assert np.array_equal(g[3], T(g[3]))
+        assert np.array_equal(g[4], T(g[4]))
+        assert np.array_equal(g[5], T(g[6]))
+        assert np.array_equal(g[7], T(g[7]))
+        assert not np.array_equal(g[0], rho)
     finally:
         pr.close()

@@ -2,10 +2,10 @@
 compiler's resource report for gfx950 (host only: hipcc cross-compiles, no GPU needed).
 
 These are performance assumptions of the kernel design, not correctness: the FP64 PPM +
-HLLD flux kernel runs three waves per SIMD (at most 168 VGPRs, and three workgroups'
-memory within the CU's 160 KiB), the FP64 time-step CT kernel three, and no other MHD
-stage kernel spills.  A different compiler can move them without changing any result;
-a failure names the budget that moved.
+HLLD flux/update kernel runs two waves per SIMD without spilling (two workgroups'
+memory within the CU's 160 KiB), the FP64 time-step CT kernel three, and no MHD stage
+kernel spills.  A different compiler can move them without changing any result; a
+failure names the budget that moved.
 """
 import re
 import subprocess
@@ -49,18 +49,18 @@ def _one(res: dict, prefix: str) -> dict:
     return hits[0]
 
 
-# mangled names: k_flux3<RECON, RS, real>, k_ct_update<CFL, IN, real, rows>
-FLUX_PPM_HLLD_F64 = "_ZN3mhd7k_flux3ILi2ELi1EdE"
+# mangled names: k_flux3<RECON, RS, IN, real>, k_ct_update<CFL, IN, real, rows>
+FLUX_PPM_HLLD_F64 = ("_ZN3mhd7k_flux3ILi2ELi1ELb0EdE", "_ZN3mhd7k_flux3ILi2ELi1ELb1EdE")
 CT_CFL_F64 = "_ZN3mhd11k_ct_updateILb1ELb0EdLi4EE"
 
 
-def test_fp64_ppm_flux_kernel_runs_three_waves(fused):
-    k = _one(fused, FLUX_PPM_HLLD_F64)
-    assert k["VGPRs"] + k.get("AGPRs", 0) <= 168, k
-    assert 3 * k["LDS Size"] <= LDS_PER_CU, k
-    assert k["Occupancy"] >= 3, k
-    # the occupancy request spills a few loop-invariant dwords, nothing more
-    assert k["ScratchSize"] <= 64, k
+@pytest.mark.parametrize("name", FLUX_PPM_HLLD_F64)
+def test_fp64_ppm_flux_kernel_runs_two_waves_without_spills(fused, name):
+    k = _one(fused, name)
+    assert k["VGPRs"] + k.get("AGPRs", 0) <= 256, k
+    assert 2 * k["LDS Size"] <= LDS_PER_CU, k
+    assert k["Occupancy"] >= 2, k
+    assert k["ScratchSize"] == 0, k
 
 
 def test_fp64_time_step_ct_kernel_runs_three_waves(fused):
@@ -72,6 +72,6 @@ def test_fp64_time_step_ct_kernel_runs_three_waves(fused):
 def test_other_stage_kernels_do_not_spill(fused):
     stage = {n: k for n, k in fused.items()
              if ("k_flux3" in n or "k_ct_update" in n) and not n.startswith(FLUX_PPM_HLLD_F64)}
-    assert len(stage) >= 12, sorted(fused)
+    assert len(stage) >= 20, sorted(fused)
     spills = {n: k["ScratchSize"] for n, k in stage.items() if k["ScratchSize"]}
     assert not spills, spills

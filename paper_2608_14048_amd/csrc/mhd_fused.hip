@@ -25,16 +25,18 @@ constexpr int TY = 4;    // rows (FP64 CT kernel that reduces the time step)
 constexpr int TY2 = 8;   // rows (other CT kernels)
 }  // namespace
 
-// Occupancy requests: none beyond two waves per SIMD for the FP64 PPM kernel.  Holding
-// it to three (168 registers) spills about 36 dwords per lane and measured 20 % slower
-// (3.48 against 2.91 ms per corrector launch at 256^3).
-template <int RECON, class R>
+// Occupancy requests (waves per SIMD): four for every FP32 kernel (at most 128
+// registers), two for the FP64 HLLD kernels with a PLM or PPM stencil, three for the
+// other FP64 kernels.  Holding the FP64 PPM + HLLD kernel to three waves (168 registers)
+// spills about 36 dwords per lane and measured 20 % slower (3.48 against 2.91 ms per
+// corrector launch at 256^3).
+template <int RECON, int RS, class R>
 struct FluxWaves {
-    static constexpr int min = RECON == 2 && sizeof(R) == 8 ? 2 : 1;
+    static constexpr int min = sizeof(R) == 4 ? 4 : (RS == 1 && RECON > 0 ? 2 : 3);
 };
 
 template <int RECON, int RS, bool IN, class R>
-__global__ __launch_bounds__(TXF* TYF) __attribute__((amdgpu_waves_per_eu(FluxWaves<RECON, R>::min)))
+__global__ __launch_bounds__(TXF* TYF) __attribute__((amdgpu_waves_per_eu(FluxWaves<RECON, RS, R>::min)))
 void k_flux3(Geo g, MhdParams P, StageArgs<R> a, int kz, unsigned int ntx, unsigned int nty, unsigned int nblk)
 {
     using Tile = FluxTile<RECON, RS, IN, R, TXF, TYF>;

@@ -237,9 +237,10 @@ enum FaceField { FX_MASS = 0, FX_EY, FX_EZ, FY_MASS, FY_EZ, FY_EX, FZ_MASS, FZ_E
 // may reach past the grid edge).  Threads: TX * TY, lanes along x first.  Per plane:
 //  - the primitives of the tile and its x/y halo are staged in LDS (one more column and
 //    row on the high side than the cells need: the tile's high faces);
-//  - every thread solves its cell's low x and y faces and the z face above its cell (the
-//    z stencil is a register pipeline fed one plane ahead); threads 0 .. TX+TY-1 also
-//    solve the tile's high faces (the row above it, the column right of it);
+//  - every thread solves its cell's low x, y and z faces (the z stencil is a register
+//    pipeline fed one plane ahead); TX + TY threads of one or two waves, a different
+//    group on each plane, also solve the tile's high faces (the row above it, the
+//    column right of it);
 //  - the faces' mass, momentum and energy fluxes meet in LDS, and every cell gets the
 //    flux divergence of eq. (fv_update) plus sources and the stage combination, in the
 //    same arithmetic as a separate update pass would use;
@@ -249,7 +250,8 @@ template <int RECON, int RS, bool IN, class R, int TX, int TY>
 struct FluxTile {
     static constexpr int SL = Stencil<RECON>::L, SR = Stencil<RECON>::R;
     static constexpr int LX = TX + SL + SR + 1, LY = TY + SL + SR + 1;
-    static constexpr int NT = TX * TY, NR = TX + TY;
+    static constexpr int NT = TX * TY, NR = TX + TY, NW = NT / 64;
+    static_assert(NT % 64 == 0 && (NW & (NW - 1)) == 0, "whole wavefronts, a power of two of them");
     static_assert(NR <= NT, "the tile's high faces need TX + TY threads");
     // FP64 PPM: keep the compiler from hoisting the stencil loads of every variable
     // ahead of the reconstructions (it would hold them all in registers at once)
@@ -297,14 +299,7 @@ struct FluxTile {
         R* Fo[NFACE];
     #pragma unroll
         for (int q = 0; q < NFACE; ++q) Fo[q] = a.F + q * n;
-        // the tile's own high faces: threads q < TX take the y face above column q, threads
-        // TX <= q < TX + TY the x face right of row q - TX (when inside the grid's range)
-        const int q = (int)threadIdx.x;
-        const bool ring_y = q < TX, ring_x = !ring_y && q < NR;
-        const int rq = ring_y ? q : q - TX;
-        const bool rneed = ring_y ? (y0 + TY <= g.ny && x0 + rq < g.nx) : (ring_x && x0 + TX <= g.nx && y0 + rq < g.ny);
-        const int rxc = ring_y ? wrap_any(x0 + rq, g.nx) : wrap_any(x0 + TX, g.nx);
-        const int ryc = ring_y ? wrap_any(y0 + TY, g.ny) : wrap_any(y0 + rq, g.ny);
+        const int wave = (int)threadIdx.x / 64, wl = (int)threadIdx.x % 64;
 
         // z pipeline of the face-frame variables (rho, v_z, v_x, v_y, p, B_x, B_y); plane
         // k's own values come from the staged plane (a direct load on the last pass)
@@ -460,21 +455,40 @@ struct FluxTile {
                 stT(a.Rc + 2 * n, c, vy * bx - vx * by);
             }
             // ---- the tile's high faces (fluxes only: their E values belong to the
-            // neighbouring tile's cells)
-            if (rneed) {
-                const unsigned int cr = (unsigned int)k * plane + (unsigned int)ryc * nx + (unsigned int)rxc;
-                if (ring_y) {
-                    const int comp[7] = {0, 2, 3, 1, 4, 7, 5};
-                    recon7(comp, [&](int v, int s) { return sw[v][TY + SL + s][rq + SL]; }, L, Rt);
-                    solve<RS>(L, Rt, ldT(a.in.b[1], cr), P, f);
-                    lds.hy[0][TY][rq] = f.d; lds.hy[1][TY][rq] = f.mt2; lds.hy[2][TY][rq] = f.mn;
-                    lds.hy[3][TY][rq] = f.mt1; lds.hy[4][TY][rq] = f.e;
-                } else {
-                    const int comp[7] = {0, 1, 2, 3, 4, 6, 7};
-                    recon7(comp, [&](int v, int s) { return sw[v][rq + SL][TX + SL + s]; }, L, Rt);
-                    solve<RS>(L, Rt, ldT(a.in.b[0], cr), P, f);
-                    lds.hx[0][rq][TX] = f.d; lds.hx[1][rq][TX] = f.mn; lds.hx[2][rq][TX] = f.mt1;
-                    lds.hx[3][rq][TX] = f.mt2; lds.hx[4][rq][TX] = f.e;
+            // neighbouring tile's cells): ring slot q < TX is the y face above column q,
+            // TX <= q < TX + TY the x face right of row q - TX.  The slots go to
+            // consecutive waves starting from one that changes from plane to plane in
+            // FP64 (no wave carries them every time), and both directions share one code path
+            // (stencil line, variable order and flux order picked per lane), so a wave
+            // solves its ring faces in one pass whatever their direction.
+            {
+                const int turn = sizeof(R) == 8 ? k - k0 : 0;  // (FP32 measured faster without)
+                const int rs = ((wave - turn) & (NW - 1)) * 64 + wl;
+                const bool ry = rs < TX;
+                const int rq = ry ? rs : rs - TX;
+                const bool rneed = ry ? (y0 + TY <= g.ny && x0 + rq < g.nx)
+                                      : (rs < NR && x0 + TX <= g.nx && y0 + rq < g.ny);
+                if (rneed) {
+                    // a tile reaching the grid's high edge owns the faces at 0
+                    const int rxc = ry ? x0 + rq : wrap_once(x0 + TX, g.nx);
+                    const int ryc = ry ? wrap_once(y0 + TY, g.ny) : y0 + rq;
+                    const unsigned int cr = (unsigned int)k * plane + (unsigned int)ryc * nx + (unsigned int)rxc;
+                    constexpr int cy[7] = {0, 2, 3, 1, 4, 7, 5}, cx[7] = {0, 1, 2, 3, 4, 6, 7};
+                    int comp[7];
+    #pragma unroll
+                    for (int v = 0; v < 7; ++v) comp[v] = ry ? cy[v] : cx[v];
+                    const int base = ry ? (TY + SL) * LX + rq + SL : (rq + SL) * LX + TX + SL;
+                    const int stride = ry ? LX : 1;
+                    const R* swf = &sw[0][0][0];
+                    recon7(comp, [&](int v, int s) { return swf[v * (LY * LX) + base + s * stride]; }, L, Rt);
+                    solve<RS>(L, Rt, ldT(ry ? a.in.b[1] : a.in.b[0], cr), P, f);
+                    if (ry) {
+                        lds.hy[0][TY][rq] = f.d; lds.hy[1][TY][rq] = f.mt2; lds.hy[2][TY][rq] = f.mn;
+                        lds.hy[3][TY][rq] = f.mt1; lds.hy[4][TY][rq] = f.e;
+                    } else {
+                        lds.hx[0][rq][TX] = f.d; lds.hx[1][rq][TX] = f.mn; lds.hx[2][rq][TX] = f.mt1;
+                        lds.hx[3][rq][TX] = f.mt2; lds.hx[4][rq][TX] = f.e;
+                    }
                 }
             }
             __syncthreads();

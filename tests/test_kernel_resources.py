@@ -3,8 +3,9 @@ compiler's resource report for gfx950 (host only: hipcc cross-compiles, no GPU n
 
 These are performance assumptions of the kernel design, not correctness: the FP64 PPM +
 HLLD flux/update kernel runs two waves per SIMD without spilling (two workgroups'
-memory within the CU's 160 KiB), the FP64 time-step CT kernel three, and no MHD stage
-kernel spills.  A different compiler can move them without changing any result; a
+memory within the CU's 160 KiB), every FP32 flux/update kernel four, the FP64 HLLE and
+donor-cell ones three, the FP64 time-step CT kernel three, and no MHD stage kernel
+spills.  A different compiler can move them without changing any result; a
 failure names the budget that moved.
 """
 import re
@@ -67,6 +68,19 @@ def test_fp64_time_step_ct_kernel_runs_three_waves(fused):
     k = _one(fused, CT_CFL_F64)
     assert k["Occupancy"] >= 3, k
     assert k["ScratchSize"] == 0, k
+
+
+def test_fp32_flux_kernels_run_four_waves_and_fp64_hlle_three(fused):
+    flux = {n: k for n, k in fused.items() if n.startswith("_ZN3mhd7k_flux3I")}
+    assert len(flux) == 24, sorted(flux)
+    for n, k in flux.items():
+        # mangled template arguments: <RECON, RS, IN, real>
+        m = re.match(r"_ZN3mhd7k_flux3ILi(\d)ELi(\d)ELb\dE([df])E", n)
+        recon, rs, real = int(m.group(1)), int(m.group(2)), m.group(3)
+        if real == "f":
+            assert k["Occupancy"] >= 4, (n, k)
+        elif rs == 0 or recon == 0:
+            assert k["Occupancy"] >= 3, (n, k)
 
 
 def test_other_stage_kernels_do_not_spill(fused):

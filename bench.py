@@ -42,27 +42,40 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, packed (the kernels here 
 STEP_ALGO_BYTES = 320.0         # bytes per zone-cycle a fully fused VL2 FP64 step must move
 STEP_ALGO_BYTES_FP32 = 180.0    # the same for the FP32-bulk form (7 FP32 fields + FP64 E)
 
+# Algorithmic bytes per cell of each stage of the VL2 step (the traffic model of the
+# fused step: each stage reads its input register once, the corrector also the base
+# register, and writes one register): predictor 8 + 8 fields, corrector 8 + 8 + 8.  The
+# roofline of the dominant kernel divides its stage's bytes by that kernel's time (the
+# kernel does the stage's reading and most of its writing; the CT kernel beside it
+# finishes the face fields).
+STAGE_ALGO_BYTES = {"predictor": 128.0, "corrector": 192.0}
+STAGE_ALGO_BYTES_FP32 = {"predictor": 72.0, "corrector": 108.0}
+
 # Algorithmic work per cell of one launch of each kernel class.  Bytes: every array the
 # kernel needs read once, every array it produces written once (FP64).  Flops: the
 # FP64 add/sub/mul/div/sqrt of the method's formulas counted once per cell (PPM shared
 # between the two faces a cell touches; compares, min/max and selects not counted).
+# stage: which stage's bytes the dominant-kernel roofline uses.
 KERNEL_ALGO = {
-    # state (8 fields) in; 3 x 7 face fields + 3 cell E fields out
-    "mhd_flux_corrector": {"bytes": (8 + 24) * 8, "flops": 1701},  # PPM + HLLD, 3 faces
-    "mhd_flux_predictor": {"bytes": (8 + 24) * 8, "flops": 1155},  # donor cell + HLLD
-    # 24 face/cell fields + base register (8) in; 8 fields out
-    "mhd_ct_update_corrector": {"bytes": (24 + 8 + 8) * 8, "flops": 192},
-    "mhd_ct_update_predictor": {"bytes": (24 + 8 + 8) * 8, "flops": 120},
+    # stage input (8 fields) and, corrector, the base register's cell fields (5) in;
+    # 5 cell fields, 9 face fields and 3 cell E fields out
+    "mhd_flux_update_corrector": {"bytes": (8 + 5 + 5 + 12) * 8, "flops": 1701 + 40, "stage": "corrector"},
+    "mhd_flux_update_predictor": {"bytes": (8 + 5 + 12) * 8, "flops": 1155 + 40, "stage": "predictor"},
+    # 12 face/cell fields and the base face fields (3) in, 3 face fields out; the
+    # corrector also reads the 5 new cell fields for the time step
+    "mhd_ct_corrector": {"bytes": (12 + 3 + 3 + 5) * 8, "flops": 152, "stage": "corrector"},
+    "mhd_ct_predictor": {"bytes": (12 + 3 + 3) * 8, "flops": 80, "stage": "predictor"},
     "cfl": {"bytes": 8 * 8, "flops": 72},
 }
 
-# FP32-bulk form: a state is 7 FP32 fields + FP64 E = 36 B, a face or cell-E field 4 B;
-# the flops are those of the FP64 table, in FP32 (E's update in FP64)
+# FP32-bulk form: a state is 7 FP32 fields + FP64 E = 36 B (cell fields: 3 x 4 + 8 = 20
+# B; face fields 12 B), a face or cell-E field 4 B; the flops are those of the FP64
+# table, in FP32 (E's update in FP64)
 KERNEL_ALGO_FP32 = {
-    "mhd_flux_corrector": {"bytes": 36 + 24 * 4, "flops": 1701},
-    "mhd_flux_predictor": {"bytes": 36 + 24 * 4, "flops": 1155},
-    "mhd_ct_update_corrector": {"bytes": 24 * 4 + 36 + 36, "flops": 192},
-    "mhd_ct_update_predictor": {"bytes": 24 * 4 + 36 + 36, "flops": 120},
+    "mhd_flux_update_corrector": {"bytes": 36 + 20 + 20 + 12 * 4, "flops": 1741, "stage": "corrector"},
+    "mhd_flux_update_predictor": {"bytes": 36 + 20 + 12 * 4, "flops": 1195, "stage": "predictor"},
+    "mhd_ct_corrector": {"bytes": 12 * 4 + 12 + 12 + 20, "flops": 152, "stage": "corrector"},
+    "mhd_ct_predictor": {"bytes": 12 * 4 + 12 + 12, "flops": 80, "stage": "predictor"},
     "cfl": {"bytes": 36, "flops": 72},
 }
 
@@ -77,16 +90,20 @@ DUST_STEP_ALGO_BYTES = 5 * DUST_FIELDS * 8
 def dust_kernel_algo(word: int) -> dict:
     """Algorithmic bytes per cell of each dust kernel class for fields of `word` bytes."""
     return {
-        "dust_fluid_pass_stage1": {"bytes": 2 * DUST_FIELDS * word},             # u in, X out
-        "dust_fluid_pass_stage2": {"bytes": 3 * DUST_FIELDS * word},             # U1, u in, X out
-        "dust_drag_stage1": {"bytes": (DUST_FIELDS + DUST_MOM) * word},          # X in, momenta out
-        "dust_drag_cfl_stage2": {"bytes": (2 * DUST_FIELDS + DUST_MOM) * word},  # X, U1 in, momenta out
+        "dust_fluid_pass_stage1": {"bytes": 2 * DUST_FIELDS * word, "stage": "stage1"},             # u in, X out
+        "dust_fluid_pass_stage2": {"bytes": 3 * DUST_FIELDS * word, "stage": "stage2"},             # U1, u in, X out
+        "dust_drag_stage1": {"bytes": (DUST_FIELDS + DUST_MOM) * word, "stage": "stage1"},          # X in, momenta out
+        "dust_drag_cfl_stage2": {"bytes": (2 * DUST_FIELDS + DUST_MOM) * word, "stage": "stage2"},  # X, U1 in, momenta out
         "cfl": {"bytes": DUST_FIELDS * 8},
     }
 
 
 DUST_KERNEL_ALGO = dust_kernel_algo(8)
 DUST_KERNEL_ALGO_FP32 = dust_kernel_algo(4)
+# the fused-step traffic model per stage: stage 1 reads u and writes U1, stage 2 reads u
+# and U1 and writes u (1440 B per zone-cycle in FP64 at 8 species)
+DUST_STAGE_BYTES = {"stage1": 2 * DUST_FIELDS * 8.0, "stage2": 3 * DUST_FIELDS * 8.0}
+DUST_STAGE_BYTES_FP32 = {"stage1": 2 * DUST_FIELDS * 4.0, "stage2": 3 * DUST_FIELDS * 4.0}
 
 WORKLOAD = "decaying MHD turbulence, periodic {n}^3, VL2+PPM+HLLD+CT, CFL 0.3, seed 0"
 
@@ -157,30 +174,66 @@ def timed_run(sim, steps: int, warmup: int, dts_in=None):
     return el, times, warm, dts
 
 
-def kernel_roofline(times, table, ncell, workload, alu_peak=None):
-    """Roofline of the kernel class with the largest device time: achieved algorithmic
-    bytes (and flops, where the table has them) per average launch duration."""
+def measured_counters(workload: str, kernel: str):
+    """VALU work and issue rates of a kernel class from the committed counter summary, if
+    it was taken on the current kernel sources (else None): VALU and FP64-arithmetic
+    wave instructions per cell, and per CU-cycle at 2.4 GHz and at the clock the kernel
+    ran at (GRBM_GUI_ACTIVE over its duration); a CU issues at most one VALU wave
+    instruction per cycle (four SIMDs, four cycles per wave64 instruction)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        if rec.get("source_digest") != source_digest():
+            return None
+        ent = rec.get("workloads", {}).get(workload, {}).get("kernels", {}).get(kernel, {})
+        out = {k: ent[k] for k in ("valu_per_cell", "fp64_per_cell", "valu_issue", "fp64_issue", "clock_ghz",
+                                   "valu_issue_at_clock", "fp64_issue_at_clock") if k in ent}
+        return out or None
+    except (OSError, ValueError, KeyError, AttributeError):
+        return None
+
+
+def kernel_roofline(times, table, ncell, workload, stage_bytes):
+    """HBM roofline of the kernel class with the largest device time: the algorithmic
+    bytes of its stage (the fused-step traffic model, bytes per cell x cells) per
+    average launch duration, against the 8 TB/s peak.  Beside it: the kernel's own
+    minimum bytes, its measured bytes per launch (rocprof FETCH_SIZE + WRITE_SIZE, when
+    taken on the current sources) and its VALU issue rates from the SQ counters."""
     dominant = max(times, key=lambda k: times[k][0])
     total_ms, launches = times[dominant]
     avg_s = total_ms / launches * 1e-3
     work = table.get(dominant, {"bytes": 0})
-    gbs = work["bytes"] * ncell / avg_s / 1e9
-    f_hbm = gbs / HBM_PEAK_GBS
+    per_cell = stage_bytes.get(work.get("stage"), work["bytes"])
+    gbs = per_cell * ncell / avg_s / 1e9
+    traffic = measured_traffic(workload, dominant, ncell)
     rf = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-          "frac": round(f_hbm, 4)}
-    f_alu = None
-    if alu_peak and "flops" in work:
-        tfl = work["flops"] * ncell / avg_s / 1e12
-        f_alu = tfl / alu_peak
-        if f_alu > f_hbm:
-            rf = {"bound": "alu", "achieved": round(tfl, 3), "peak": alu_peak, "unit": "TFLOP/s",
-                  "frac": round(f_alu, 4)}
-    rf.update({"traffic": measured_traffic(workload, dominant, ncell), "kernel": dominant,
-               "avg_launch_ms": round(total_ms / launches, 4), "launches": launches,
-               "hbm_frac": round(f_hbm, 4)})
-    if f_alu is not None:
-        rf["alu_frac"] = round(f_alu, 4)
+          "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dominant,
+          "algo_bytes_per_cell": per_cell,
+          "algo_basis": f"{work.get('stage', 'kernel')} stage of the fused-step traffic model",
+          "kernel_min_bytes_per_cell": work["bytes"],
+          "avg_launch_ms": round(total_ms / launches, 4), "launches": launches}
+    if traffic is not None:
+        rf["traffic_over_algo"] = round(traffic / (per_cell * ncell), 3)
+    cnt = measured_counters(workload, dominant)
+    if cnt:
+        rf["counters"] = cnt
     return rf
+
+
+def step_traffic(workload: str, times, ncell: int, steps: int, algo_bytes_per_cell: float):
+    """Measured HBM bytes of one step (every kernel class, per-launch bytes x launches
+    per step) over the step's algorithmic bytes, when the counters were taken on the
+    current sources (else None)."""
+    total = 0.0
+    for k, (_, launches) in times.items():
+        b = measured_traffic(workload, k, ncell)
+        if b is None:
+            return None
+        total += b * launches / steps
+    return {"bytes_per_step": round(total), "over_algo": round(total / (algo_bytes_per_cell * ncell), 3)}
 
 
 def dust_leg(n: int, steps: int, warmup: int, seed: int = 0, fp32: bool = True):
@@ -206,7 +259,7 @@ def dust_leg(n: int, steps: int, warmup: int, seed: int = 0, fp32: bool = True):
                        f"g = 0.05, periodic {n}^3, IMEX2P+PLM+HLLE/Rusanov, CFL 0.3, seed {seed}",
            "value": round(value, 2), "unit": "Mzone-cycles/s", "dtype": "f64", "steps": steps,
            "ms_per_step": round(el * 1e3 / steps, 4),
-           "roofline": kernel_roofline(times, DUST_KERNEL_ALGO, ncell, f"dust{n}_fp64"),
+           "roofline": kernel_roofline(times, DUST_KERNEL_ALGO, ncell, f"dust{n}_fp64", DUST_STAGE_BYTES),
            "step_hbm_roofline": {"algo_bytes_per_zone_cycle": DUST_STEP_ALGO_BYTES,
                                  "frac": round(value * 1e6 * DUST_STEP_ALGO_BYTES
                                                / (HBM_PEAK_GBS * 1e9), 4)},
@@ -230,7 +283,8 @@ def dust_leg(n: int, steps: int, warmup: int, seed: int = 0, fp32: bool = True):
                    "ms_per_step": round(el * 1e3 / steps, 4), "dtype": "f32 (drag solve in f64)",
                    "l1_rel_vs_fp64": {k: float(f"{v:.3e}") for k, v in l1.items()},
                    "compared_after_steps": len(warm) + steps,
-                   "roofline": kernel_roofline(times, DUST_KERNEL_ALGO_FP32, ncell, f"dust{n}_fp32"),
+                   "roofline": kernel_roofline(times, DUST_KERNEL_ALGO_FP32, ncell, f"dust{n}_fp32",
+                                               DUST_STAGE_BYTES_FP32),
                    "step_hbm_roofline": {"algo_bytes_per_zone_cycle": DUST_STEP_ALGO_BYTES // 2,
                                          "frac": round(v32 * 1e6 * (DUST_STEP_ALGO_BYTES // 2)
                                                        / (HBM_PEAK_GBS * 1e9), 4)},
@@ -255,16 +309,61 @@ def paper_config_leg(shape, steps: int, warmup: int, precisions=("fp64", "fp32_b
     out = {"workload": f"oblique linear fast wave, {shape[0]}x{shape[1]}x{shape[2]} "
                        "periodic box, RK2+PLM+HLLE+CT, CFL 0.3, one block",
            "paper_mzcps_context": PAPER_TABLE}
+    ref, seq = None, None
     for prec in precisions:
         sim = Sim(shape, length, scheme=dict(recon="plm", riemann="hlle", integ="rk2",
                                              courant=0.3, prec=prec))
         sim.set_state(state)
-        el, times, _, _ = timed_run(sim, steps, warmup)
+        # the FP32-bulk run takes the FP64 run's dt sequence, so the two end states compare
+        el, times, warm, dts = timed_run(sim, steps, warmup, seq)
+        got = sim.state(device=True)
         sim.close()
         out[prec] = {"value": round(ncell * steps / el / 1e6, 2), "unit": "Mzone-cycles/s",
                      "steps": steps, "ms_per_step": round(el * 1e3 / steps, 4),
                      "kernel_ms_per_step": {k: round(v[0] / steps, 4)
                                             for k, v in sorted(times.items())}}
+        if ref is None:
+            ref, seq = got, list(warm) + list(dts)
+        else:
+            # the wave is a 1e-6 perturbation: measure the error on the perturbation, against
+            # the FP64 GPU run (which matches the oracle to 1e-12 per step)
+            base, _ = I.linear_wave(amp=0.0, along="box", shape=shape)
+            out[prec]["l1_rel_vs_fp64"] = l1_classes(got, ref, base)
+            out[prec]["l1_reference"] = (f"the FP64 run on the same dt sequence after {len(seq)} steps; "
+                                         "relative to the L1 norm of the wave's perturbation")
+        del got
+    return out
+
+
+def l1_classes_blocks(got, ref, shapes):
+    """l1_classes over a batch state (the blocks' canonical states one after another)."""
+    rows = {"rho": [0], "M": [1, 2, 3], "E": [4], "B": [5, 6, 7]}
+    num = {k: 0.0 for k in rows}
+    den = {k: 0.0 for k in rows}
+    at = 0
+    for sh in shapes:
+        m = int(sh[0] * sh[1] * sh[2])
+        g = got[at:at + 8 * m].reshape(8, m)
+        r = ref[at:at + 8 * m].reshape(8, m)
+        for k, v in rows.items():
+            num[k] += float((g[v] - r[v]).abs().sum())
+            den[k] += float(r[v].abs().sum())
+        at += 8 * m
+    return {k: float(f"{num[k] / den[k]:.3e}") for k in rows}
+
+
+def l1_classes(got, ref, base=None):
+    """Relative L1 difference of each MHD conserved class (rho, M, E, B) between two
+    device states; with base, relative to the L1 norm of ref - base (a perturbation)."""
+    import torch
+
+    g, r = got.reshape(8, -1), ref.reshape(8, -1)
+    b = None if base is None else torch.as_tensor(base, device=r.device).reshape(8, -1)
+    rows = {"rho": [0], "M": [1, 2, 3], "E": [4], "B": [5, 6, 7]}
+    out = {}
+    for k, v in rows.items():
+        den = (r[v] - b[v]).abs().sum() if b is not None else r[v].abs().sum()
+        out[k] = float(f"{float((g[v] - r[v]).abs().sum() / den):.3e}")
     return out
 
 
@@ -303,11 +402,23 @@ def batch_leg(nblocks: int, steps: int, warmup: int, prec: str = "fp32_bulk", se
 
     bt.set_state(states)
     el_tuned = run_batch()
+    got32 = bt.state(device=True)
     bt.set_tile_shapes(default_shapes)
     bt.set_state(states)
     el_default = run_batch()
     bt.close()
     del bt
+    # the same blocks and time steps in FP64 (default shapes): the reference of the
+    # FP32-bulk batch's error
+    l1 = None
+    if prec == "fp32_bulk" and got32 is not None:
+        b64 = Batch(shapes, scheme=dict(scheme, prec="fp64"))
+        b64.set_state(states)
+        for _ in range(warmup + steps):
+            b64.step(dts)
+        l1 = l1_classes_blocks(got32, b64.state(device=True), shapes)
+        b64.close()
+        del b64
     sims = []
     for sh, st in zip(shapes, states):
         sim = Sim(sh, tuple(v / max(sh) for v in sh), scheme=scheme)
@@ -335,6 +446,8 @@ def batch_leg(nblocks: int, steps: int, warmup: int, prec: str = "fp32_bulk", se
             "separate_launches_value": mz(el_sep),
             "separate_launches_ms_per_step": round(el_sep * 1e3 / steps, 4),
             "speedup_vs_separate": round(el_sep / el_tuned, 2),
+            "l1_rel_vs_fp64": l1,
+            "l1_reference": f"the same {nblocks} blocks in FP64 on the same dt sequence after {warmup + steps} steps",
             "tuned_shape_per_x_extent": {str(x): int(chosen[[sh[0] for sh in shapes].index(x)]) for x in classes},
             "fastest_alone_per_x_extent": {str(x): int(np.argmin(tune_ms[q])) for q, x in enumerate(classes)},
             "tune_ms_per_pass": {str(x): [round(float(v), 4) for v in tune_ms[q]] for q, x in enumerate(classes)}}
@@ -369,9 +482,20 @@ def closure_leg(seeds=(900, 901), steps: int = 8):
                              "plain_2x": mz(times["plain_2x_ms"])}}
 
 
-def cpu_baseline(n: int, state, max_seconds: float = 30.0):
-    """The oracle as it stands on a bounded sample: as many steps of the same workload
-    as fit in about max_seconds (at least one)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_rate(n: int, state, max_seconds: float):
+    """Steps of the oracle on the n^3 turbulence workload from `state` until about
+    max_seconds have passed (at least one); returns (Mzone-cycles/s, steps, seconds)."""
     import oracle
 
     cfg = oracle.make_cfg((n, n, n), recon="ppm", riemann="hlld", integ="vl2", courant=0.3)
@@ -385,11 +509,32 @@ def cpu_baseline(n: int, state, max_seconds: float = 30.0):
         el = time.perf_counter() - t0
         if el * (steps + 1) / steps > max_seconds:
             break
-    value = n ** 3 * steps / el / 1e6
-    return {"value": round(value, 4), "unit": "Mzone-cycles/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+    return n ** 3 * steps / el / 1e6, steps, el
+
+
+def cpu_baseline(n: int, state, max_seconds: float = 30.0, seed: int = 0):
+    """The oracle as it stands on bounded samples: all threads on as many steps of the
+    same n^3 workload as fit in about max_seconds, then one thread on the same recipe at
+    64^3 for about a third of that (one 256^3 step takes a single core about 40 s)."""
+    import oracle
+
+    from paper_2608_14048_amd import inputs as I
+
+    threads = oracle.num_threads()
+    value, steps, el = oracle_rate(n, state, max_seconds)
+    n1 = 64
+    oracle.set_num_threads(1)
+    try:
+        v1, s1, e1 = oracle_rate(n1, I.turbulence(n1, seed=seed), max_seconds / 3.0)
+    finally:
+        oracle.set_num_threads(threads)
+    return {"value": round(value, 4), "unit": "Mzone-cycles/s", "cores": threads,
+            "kind": "oracle", "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"{steps} step(s) of the {n}^3 workload from the same initial state "
-                      f"({el:.1f} s, OpenMP over k-planes)"}
+                      f"({el:.1f} s, {threads} OpenMP threads over k-planes)",
+            "single_thread": {"value": round(v1, 4), "unit": "Mzone-cycles/s", "cores": 1,
+                              "sample": f"{s1} step(s) of the same recipe at {n1}^3 (seed {seed}), "
+                                        f"{e1:.1f} s on one thread"}}
 
 
 def fp32_leg(n, state, warm_dts, dts, ref64):
@@ -416,7 +561,7 @@ def fp32_leg(n, state, warm_dts, dts, ref64):
             "l1_rel_vs_fp64": {k: float(f"{v:.3e}") for k, v in l1.items()},
             "compared_after_steps": len(warm_dts) + steps,
             "roofline": kernel_roofline(times, KERNEL_ALGO_FP32, n ** 3, f"turb{n}_fp32_bulk",
-                                        FP32_VECTOR_PEAK_TFLOPS),
+                                        STAGE_ALGO_BYTES_FP32),
             "step_hbm_roofline": {"algo_bytes_per_zone_cycle": STEP_ALGO_BYTES_FP32,
                                   "frac": round(value * 1e6 * STEP_ALGO_BYTES_FP32 / (HBM_PEAK_GBS * 1e9), 4)},
             "kernel_ms_per_step": {k: round(v[0] / steps, 4) for k, v in sorted(times.items())}}
@@ -485,9 +630,9 @@ def main():
     ncell = n ** 3
     value = ncell * args.steps / elapsed / 1e6
     ms_per_step = elapsed * 1e3 / args.steps
-    # roofline of the kernel class with the largest device time, against the resource
-    # it is closer to saturating (HBM bytes or FP64 vector flops)
-    roofline = kernel_roofline(times, KERNEL_ALGO, ncell, f"turb{n}_fp64", FP64_VECTOR_PEAK_TFLOPS)
+    # HBM roofline of the kernel class with the largest device time (its stage's bytes of
+    # the fused-step traffic model over its launch time)
+    roofline = kernel_roofline(times, KERNEL_ALGO, ncell, f"turb{n}_fp64", STAGE_ALGO_BYTES)
     kernel_ms = {k: round(v[0] / args.steps, 4) for k, v in sorted(times.items())}
 
     out = {
@@ -508,7 +653,9 @@ def main():
                    "courant": 0.3, "parallelism": "single GPU"},
         "roofline": roofline,
         "step_hbm_roofline": {"algo_bytes_per_zone_cycle": STEP_ALGO_BYTES,
-                              "frac": round(value * 1e6 * STEP_ALGO_BYTES / (HBM_PEAK_GBS * 1e9), 4)},
+                              "frac": round(value * 1e6 * STEP_ALGO_BYTES / (HBM_PEAK_GBS * 1e9), 4),
+                              "measured": step_traffic(f"turb{n}_fp64", times, ncell, args.steps,
+                                                       STEP_ALGO_BYTES)},
         "kernel_ms_per_step": kernel_ms,
     }
     if copy_gbs is not None:
@@ -528,7 +675,7 @@ def main():
         out["closure"] = closure_leg()
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(n, state, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(n, state, args.cpu_seconds, args.seed)
     print(json.dumps(out), flush=True)
 
 

@@ -12,6 +12,8 @@ coarse resolution advance on the same dt sequence; each is compared with the fil
 fine state after every step (relative L1 per conserved class).
 
     python -m paper_2608_14048_amd.learned --out closure_64.npz      (train, on a GPU)
+    python -m paper_2608_14048_amd.learned --eval-sizes paper_2608_14048_amd/data/closure_64.npz
+        (the closure at 64^3 against plain runs at 72^3 and 80^3 to the same time)
 """
 from __future__ import annotations
 
@@ -244,6 +246,80 @@ def evaluate(cl, seeds, nc=64, r=4, steps=8):
     return res, {"plain_ms": 1e3 * t_plain / cnt, "closure_ms": 1e3 * t_clos / cnt, "plain_2x_ms": 1e3 * t_two / cnt}
 
 
+def evaluate_sizes(cl, seeds, sizes=(72, 80), nc=64, r=4, steps=8):
+    """Plain runs at other resolutions against the closure at nc^3, to the same time.
+
+    For each seed the plain and the closure run at nc^3 take `steps` CFL steps from the
+    fine state filtered to nc^3, reaching time T.  A plain run at n^3 for each n in
+    `sizes` starts from the same recipe and seed generated at r*n (its own realisation
+    at that resolution) filtered to n^3, and advances to T with its own CFL steps (the
+    last one shortened), its fine run alongside.  Every run is compared at T with its
+    own filtered fine state.  Returns {run: {"l1": mean relative L1 per class,
+    "ms_to_T": mean GPU-synchronised wall time of the coarse steps, "steps": mean
+    step count}}."""
+    import torch
+    out = {}
+
+    def add(name, l1, ms, nsteps):
+        e = out.setdefault(name, {"l1": [], "ms_to_T": [], "steps": []})
+        e["l1"].append(l1)
+        e["ms_to_T"].append(ms)
+        e["steps"].append(nsteps)
+
+    for seed in seeds:
+        f = FineToCoarse(seed, nc, r)
+        st0 = f.filtered()
+        plain = B.Sim((nc,) * 3, scheme=SCHEME)
+        clos = B.Sim((nc,) * 3, scheme=SCHEME)
+        plain.set_state(st0)
+        clos.set_state(st0)
+        T = t_p = t_c = 0.0
+        for k in range(steps):
+            dt = plain.dt_cfl()
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            plain.step(dt)
+            torch.cuda.synchronize()
+            b = time.perf_counter()
+            cl.step(clos, dt)
+            torch.cuda.synchronize()
+            c = time.perf_counter()
+            t_p += b - a
+            t_c += c - b
+            T += dt
+            f.advance(dt)
+        ref = f.filtered()
+        add(f"plain_{nc}", l1_rel(plain.state(device=True), ref, nc ** 3), 1e3 * t_p, steps)
+        add(f"closure_{nc}", l1_rel(clos.state(device=True), ref, nc ** 3), 1e3 * t_c, steps)
+        for s_ in (plain, clos):
+            s_.close()
+        f.close()
+        for n in sizes:
+            g = FineToCoarse(seed, n, r)
+            run = B.Sim((n,) * 3, scheme=SCHEME)
+            run.set_state(g.filtered())
+            t = el = 0.0
+            cnt = 0
+            while t < T * (1 - 1e-12):
+                dt = min(run.dt_cfl(), T - t)
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                run.step(dt)
+                torch.cuda.synchronize()
+                el += time.perf_counter() - a
+                g.advance(dt)
+                t += dt
+                cnt += 1
+            add(f"plain_{n}", l1_rel(run.state(device=True), g.filtered(), n ** 3), 1e3 * el, cnt)
+            run.close()
+            g.close()
+        _say(f"seed {seed}: T = {T:.5f}, " + ", ".join(f"{k} E {v['l1'][-1]['E']:.3e} ({v['ms_to_T'][-1]:.2f} ms)"
+                                                         for k, v in out.items()))
+    return {k: {"l1": {c: float(np.mean([e[c] for e in v["l1"]])) for c in ROWS},
+                "ms_to_T": float(np.mean(v["ms_to_T"])), "steps": float(np.mean(v["steps"]))}
+            for k, v in out.items()}
+
+
 def summary(res):
     """Mean over seeds of the relative L1 error after the last step, per run and class."""
     out = {}
@@ -254,13 +330,26 @@ def summary(res):
 
 def main():
     ap = argparse.ArgumentParser(description="train the learned closure on this solver's own data")
-    ap.add_argument("--out", required=True)
+    ap.add_argument("--out", help="train and write the weights and record here")
+    ap.add_argument("--eval-sizes", metavar="WEIGHTS",
+                    help="instead of training: the closure in WEIGHTS against plain runs at other "
+                         "resolutions, to the same time (evaluate_sizes)")
+    ap.add_argument("--sizes", type=int, nargs="+", default=[72, 80])
+    ap.add_argument("--seeds", type=int, nargs="+", default=[900, 901, 902, 903])
     ap.add_argument("--nc", type=int, default=64)
     ap.add_argument("--r", type=int, default=4)
     ap.add_argument("--train-seeds", type=int, default=128)
     ap.add_argument("--eval-seeds", type=int, default=16)
     ap.add_argument("--iters", type=int, default=12000)
     args = ap.parse_args()
+    if args.eval_sizes:
+        cl, meta = load(args.eval_sizes)
+        res = evaluate_sizes(cl, args.seeds, tuple(args.sizes), meta["nc"], meta["r"])
+        cl.close()
+        print(json.dumps({"seeds": args.seeds, "runs": res}))
+        return
+    if not args.out:
+        ap.error("--out or --eval-sizes is required")
     train_seeds = list(range(100, 100 + args.train_seeds))
     eval_seeds = list(range(900, 900 + args.eval_seeds))
     samples = make_samples(train_seeds, args.nc, args.r)

@@ -13,11 +13,12 @@
 //
 // Network: 4 periodic 3x3x3 convolutions, widths 8 -> 32 -> 32 -> 32 -> 18, ReLU after
 // the first three.  Every convolution is an implicit GEMM on the matrix cores: BF16
-// operands, FP32 accumulation, v_mfma_f32_16x16x16_bf16.  Activations are stored
-// channel-last ([voxel][channel], channels padded to 16 or 32) so that one lane's four
-// K values are one 8-byte load.  A wavefront owns 64 voxels (4 row blocks of 16 along
-// x) x 32 output channels (2 column blocks): 8 accumulators, 27 taps x (C_in / 16) K
-// steps of 8 MFMAs.  The backward data pass is the same kernel on reflected,
+// operands, FP32 accumulation, v_mfma_f32_16x16x32_bf16 for the 32-channel inputs and
+// v_mfma_f32_16x16x16_bf16 for the first layer's 16 (8 padded).  Activations are
+// stored channel-last ([voxel][channel], channels padded to 16 or 32) so that one
+// lane's K values are one or two 8-byte loads.  A wavefront owns 64 voxels (4 row
+// blocks of 16 along x) x 32 output channels (2 column blocks): 8 accumulators, 27
+// taps x one K step of 8 MFMAs.  The backward data pass is the same kernel on reflected,
 // transposed weights with the ReLU mask of the layer below; the weight gradient is a
 // GEMM over voxels per tap (MFMA with K along voxels) added atomically into FP32.
 // Master weights and Adam moments are FP32; the BF16 copies are refreshed after each
@@ -50,7 +51,20 @@ constexpr int kVoxPerWave = 64;
 
 typedef unsigned short bf16_t;
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+
+// One 16 x 16 output block times a K chunk: 32 channels per instruction
+// (v_mfma_f32_16x16x32_bf16: lane l holds A row l % 16 and B column l % 16 at K
+// 8 (l / 16) + 0..7; checked on the device) where the layer input is a multiple of 32
+// channels wide, else 16 (v_mfma_f32_16x16x16_bf16, K 4 (l / 16) + 0..3).  Both
+// convolution forms step through K the same way, so they give the same bits.
+__device__ __forceinline__ f4 mfma_k32(s4 alo, s4 ahi, s8 b, f4 c)
+{
+    const s8 a = {alo[0], alo[1], alo[2], alo[3], ahi[0], ahi[1], ahi[2], ahi[3]};
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+}
 
 constexpr size_t layer_w(int l) { return (size_t)27 * kCin[l] * kCout[l]; }
 constexpr size_t layer_params(int l) { return layer_w(l) + kCout[l]; }
@@ -147,18 +161,36 @@ __global__ __launch_bounds__(kThreads) void k_conv(Geo g, const bf16_t* __restri
         unsigned int vs[4];
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) vs[rb] = tap_voxel(g, bx[rb], by[rb], bz[rb], t);
+        if constexpr (CINP % 32 == 0) {
+            const int lk8 = (lane >> 4) * 8;
 #pragma unroll
-        for (int kc = 0; kc < CINP / 16; ++kc) {
-            s4 bf[2];
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb)
-                bf[cb] = *reinterpret_cast<const s4*>(B + ((size_t)(t * kNPad + cb * 16 + lr) * CINP + kc * 16 + lk));
-#pragma unroll
-            for (int rb = 0; rb < 4; ++rb) {
-                const s4 af = *reinterpret_cast<const s4*>(X + ((size_t)vs[rb] * CINP + kc * 16 + lk));
+            for (int kc = 0; kc < CINP / 32; ++kc) {
+                s8 bf[2];
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb)
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bf[cb], acc[rb][cb], 0, 0, 0);
+                    bf[cb] = *reinterpret_cast<const s8*>(B + ((size_t)(t * kNPad + cb * 16 + lr) * CINP + kc * 32 + lk8));
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    const bf16_t* xa = X + ((size_t)vs[rb] * CINP + kc * 32 + lk8);
+                    const s4 alo = *reinterpret_cast<const s4*>(xa), ahi = *reinterpret_cast<const s4*>(xa + 4);
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_k32(alo, ahi, bf[cb], acc[rb][cb]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int kc = 0; kc < CINP / 16; ++kc) {
+                s4 bf[2];
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    bf[cb] = *reinterpret_cast<const s4*>(B + ((size_t)(t * kNPad + cb * 16 + lr) * CINP + kc * 16 + lk));
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    const s4 af = *reinterpret_cast<const s4*>(X + ((size_t)vs[rb] * CINP + kc * 16 + lk));
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb)
+                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bf[cb], acc[rb][cb], 0, 0, 0);
+                }
             }
         }
     }
@@ -238,19 +270,38 @@ __global__ __launch_bounds__(kThreads) void k_conv_lds(Geo g, const bf16_t* __re
         for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
     for (int t = 0; t < 27; ++t) {
         const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+        if constexpr (CINP % 32 == 0) {
+            const int lk8 = (lane >> 4) * 8;
 #pragma unroll
-        for (int kc = 0; kc < CINP / 16; ++kc) {
-            s4 bf[2];
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb)
-                bf[cb] = *reinterpret_cast<const s4*>(B + ((size_t)(t * kNPad + cb * 16 + lr) * CINP + kc * 16 + lk));
-#pragma unroll
-            for (int rb = 0; rb < NRB; ++rb) {
-                const s4 af = *reinterpret_cast<const s4*>(
-                    &sA[TZ * w + rb / 4 + dz + 1][rb % 4 + dy + 1][lr + dx + 1][kc * 16 + lk]);
+            for (int kc = 0; kc < CINP / 32; ++kc) {
+                s8 bf[2];
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb)
-                    acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bf[cb], acc[rb][cb], 0, 0, 0);
+                    bf[cb] = *reinterpret_cast<const s8*>(B + ((size_t)(t * kNPad + cb * 16 + lr) * CINP + kc * 32 + lk8));
+#pragma unroll
+                for (int rb = 0; rb < NRB; ++rb) {
+                    // two 8-byte reads: the padded LDS rows are 8-byte aligned only
+                    const bf16_t* xa = &sA[TZ * w + rb / 4 + dz + 1][rb % 4 + dy + 1][lr + dx + 1][kc * 32 + lk8];
+                    const s4 alo = *reinterpret_cast<const s4*>(xa), ahi = *reinterpret_cast<const s4*>(xa + 4);
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_k32(alo, ahi, bf[cb], acc[rb][cb]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int kc = 0; kc < CINP / 16; ++kc) {
+                s4 bf[2];
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+                    bf[cb] = *reinterpret_cast<const s4*>(B + ((size_t)(t * kNPad + cb * 16 + lr) * CINP + kc * 16 + lk));
+#pragma unroll
+                for (int rb = 0; rb < NRB; ++rb) {
+                    const s4 af = *reinterpret_cast<const s4*>(
+                        &sA[TZ * w + rb / 4 + dz + 1][rb % 4 + dy + 1][lr + dx + 1][kc * 16 + lk]);
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb)
+                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bf[cb], acc[rb][cb], 0, 0, 0);
+                }
             }
         }
     }

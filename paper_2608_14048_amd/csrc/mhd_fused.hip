@@ -32,7 +32,7 @@ constexpr int TY2 = 8;   // rows (other CT kernels)
 // corrector launch at 256^3).
 template <int RECON, int RS, class R>
 struct FluxWaves {
-    static constexpr int min = sizeof(R) == 4 ? 4 : (RS == 1 && RECON > 0 ? 2 : 3);
+    static constexpr int min = sizeof(R) == 4 ? 4 : (RS == 1 && RECON == 1 ? 2 : 3);
 };
 
 template <int RECON, int RS, bool IN, class R>

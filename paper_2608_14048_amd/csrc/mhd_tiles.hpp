@@ -30,6 +30,8 @@
 // access is a contiguous row segment of TX elements.
 #pragma once
 
+#include <type_traits>
+
 #include "launch.hpp"
 #include "physics.hpp"
 
@@ -245,6 +247,39 @@ struct ZPipe<2, R> {
     }
 };
 
+// The PPM pipeline without the value of plane k + 1 among its state: push takes it
+// beside that of plane k + 2 (loaded again rather than carried, for the FP64 kernel,
+// whose third wave per SIMD needs the registers).  The same arithmetic as ZPipe<2>.
+template <class R>
+struct ZPipeLean {
+    static constexpr int AHEAD = 2, PRIME = 5;  // planes k0-3 .. k0+1
+    R m0, ilo, apl;  // slope(k), a_{k-1/2}, a_+(k-1)
+    __device__ void prime(const R* a)
+    {
+        const R s1 = cw_slope(a[0], a[1], a[2]);
+        const R s2 = cw_slope(a[1], a[2], a[3]);
+        const R s3 = cw_slope(a[2], a[3], a[4]);
+        R lo = cw_interface(a[1], a[2], s1, s2);  // a_{k0-3/2}
+        R hi = cw_interface(a[2], a[3], s2, s3);  // a_{k0-1/2}
+        ilo = hi;
+        cw_limit(a[2], lo, hi);                   // cell k0-1
+        apl = hi;
+        m0 = s3;
+    }
+    __device__ void push(R ak, R a1, R a, R& aL, R& aR)
+    {
+        const R m1 = cw_slope(ak, a1, a);         // slope of cell k+1
+        R lo = ilo;
+        R hi = cw_interface(ak, a1, m0, m1);      // a_{k+1/2}
+        ilo = hi;
+        cw_limit(ak, lo, hi);                     // cell k
+        aL = apl;
+        aR = lo;
+        apl = hi;
+        m0 = m1;
+    }
+};
+
 // Stage-kernel arguments: fluxes of `in`; out = g0 in + g1 base + bdt L(in) for the
 // cell fields (rho, M, E), written by FluxTile; the face fields are updated by CtTile
 // from the edge EMFs that the face values written to F and Rc give.
@@ -285,6 +320,11 @@ struct FluxTile {
     // FP64 PPM: keep the compiler from hoisting the stencil loads of every variable
     // ahead of the reconstructions (it would hold them all in registers at once)
     static constexpr bool kFence = RECON == 2 && sizeof(R) == 8;
+    // FP64 PPM: the z pipeline reloads plane k + 1 instead of carrying it, and the x/y
+    // part of a cell's flux divergence is read from LDS when the cell is completed (one
+    // more barrier per plane) instead of being carried to the next pass: 24 fewer
+    // registers, which lets the kernel run three waves per SIMD
+    static constexpr bool kLean = RECON == 2 && sizeof(R) == 8;
     struct Lds {
         R sw[8][LY][LX];         // primitives of the plane
         R hx[5][TY][TX + 1];     // fluxes through the x faces of the plane's rows
@@ -311,7 +351,7 @@ struct FluxTile {
     __device__ static void run(const Geo& g, const MhdParams& P, const StageArgs<R>& a, int x0, int y0,
                                int k0, int k1, Lds& lds)
     {
-        using Pipe = ZPipe<RECON, R>;
+        using Pipe = std::conditional_t<kLean, ZPipeLean<R>, ZPipe<RECON, R>>;
         auto& sw = lds.sw;
         const int lane = (int)threadIdx.x % TX, row = (int)threadIdx.x / TX;
         const int i = x0 + lane, j = y0 + row;
@@ -350,10 +390,10 @@ struct FluxTile {
         // carried from one plane to the next: the x/y part of the flux divergence of the
         // cell below (mass and momenta in R, energy in FP64) and the z flux through its
         // low face (mass, M_x, M_y, M_z, E)
-        R acc[4], fzp[5];
+        R acc[kLean ? 1 : 4], fzp[5];
         double accE = 0.0;
     #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] = R(0);
+        for (int v = 0; v < (kLean ? 1 : 4); ++v) acc[v] = R(0);
     #pragma unroll
         for (int v = 0; v < 5; ++v) fzp[v] = R(0);
 
@@ -362,7 +402,7 @@ struct FluxTile {
         // the chunk's last cell
         for (int k = k0; k <= k1; ++k) {
             const bool full = k < k1;
-            Prim8<R> wk{}, wz{};
+            Prim8<R> wk{}, wz{}, wz1{};
             if (full) {
                 // stage the primitives of plane k (tile + x/y halos, corners skipped); the
                 // staging waves get issue priority so their loads go out ahead of the
@@ -382,6 +422,7 @@ struct FluxTile {
             }
             // newest plane of the z pipeline (donor cell needs none beyond plane k)
             if constexpr (Pipe::AHEAD > 0) wz = load_prims(g, P, a.in, ic, jc, wrap_any(k + Pipe::AHEAD, g.nz));
+            if constexpr (kLean) wz1 = load_prims(g, P, a.in, ic, jc, wrap_any(k + 1, g.nz));
             if (full) {
                 __syncthreads();
                 __builtin_amdgcn_s_setprio(0);
@@ -394,13 +435,19 @@ struct FluxTile {
             // ---- z face k - 1/2 from the pipeline: (rho, vz, vx, vy, p, Bx, By)
             {
                 const int r0 = row + SL, c0 = lane + SL;
-                zp[0].push(full ? sw[0][r0][c0] : wk.d, wz.d, L.d, Rt.d);
-                zp[1].push(full ? sw[3][r0][c0] : wk.vz, wz.vz, L.vn, Rt.vn);
-                zp[2].push(full ? sw[1][r0][c0] : wk.vx, wz.vx, L.vt1, Rt.vt1);
-                zp[3].push(full ? sw[2][r0][c0] : wk.vy, wz.vy, L.vt2, Rt.vt2);
-                zp[4].push(full ? sw[4][r0][c0] : wk.p, wz.p, L.p, Rt.p);
-                zp[5].push(full ? sw[5][r0][c0] : wk.bx, wz.bx, L.bt1, Rt.bt1);
-                zp[6].push(full ? sw[6][r0][c0] : wk.by, wz.by, L.bt2, Rt.bt2);
+                auto push = [&](Pipe& zpv, R ak, R a1, R a2, R& l, R& r) {
+                    if constexpr (kLean)
+                        zpv.push(ak, a1, a2, l, r);
+                    else
+                        zpv.push(ak, a2, l, r);
+                };
+                push(zp[0], full ? sw[0][r0][c0] : wk.d, wz1.d, wz.d, L.d, Rt.d);
+                push(zp[1], full ? sw[3][r0][c0] : wk.vz, wz1.vz, wz.vz, L.vn, Rt.vn);
+                push(zp[2], full ? sw[1][r0][c0] : wk.vx, wz1.vx, wz.vx, L.vt1, Rt.vt1);
+                push(zp[3], full ? sw[2][r0][c0] : wk.vy, wz1.vy, wz.vy, L.vt2, Rt.vt2);
+                push(zp[4], full ? sw[4][r0][c0] : wk.p, wz1.p, wz.p, L.p, Rt.p);
+                push(zp[5], full ? sw[5][r0][c0] : wk.bx, wz1.bx, wz.bx, L.bt1, Rt.bt1);
+                push(zp[6], full ? sw[6][r0][c0] : wk.by, wz1.by, wz.by, L.bt2, Rt.bt2);
             }
             if (live) {
                 solve<RS>(L, Rt, ldT(a.in.b[2], c), P, f);
@@ -415,9 +462,26 @@ struct FluxTile {
                     // stage combination
                     const unsigned int cb = (unsigned int)(k - 1) * plane + (unsigned int)jc * nx + (unsigned int)ic;
                     R Lc[4];
+                    double LE;
+                    if constexpr (kLean) {
+                        // the x/y part from the fluxes of plane k - 1, still in LDS (the
+                        // same expressions as the carried form)
     #pragma unroll
-                    for (int v = 0; v < 4; ++v) Lc[v] = -(acc[v] + (fz[v] - fzp[v]) * idz);
-                    double LE = -(accE + ((double)fz[4] - (double)fzp[4]) * g.inv_dx[2]);
+                        for (int v = 0; v < 4; ++v) {
+                            const R fx = (lds.hx[v][row][lane + 1] - lds.hx[v][row][lane]) * idx;
+                            const R fy = (lds.hy[v][row + 1][lane] - lds.hy[v][row][lane]) * idy;
+                            const R axy = fx + fy;
+                            Lc[v] = -(axy + (fz[v] - fzp[v]) * idz);
+                        }
+                        const double fx = ((double)lds.hx[4][row][lane + 1] - (double)lds.hx[4][row][lane]) * g.inv_dx[0];
+                        const double fy = ((double)lds.hy[4][row + 1][lane] - (double)lds.hy[4][row][lane]) * g.inv_dx[1];
+                        const double axyE = fx + fy;
+                        LE = -(axyE + ((double)fz[4] - (double)fzp[4]) * g.inv_dx[2]);
+                    } else {
+    #pragma unroll
+                        for (int v = 0; v < 4; ++v) Lc[v] = -(acc[v] + (fz[v] - fzp[v]) * idz);
+                        LE = -(accE + ((double)fz[4] - (double)fzp[4]) * g.inv_dx[2]);
+                    }
                     R o[4];
                     double oE;
                     if (IN) {
@@ -447,6 +511,9 @@ struct FluxTile {
                 for (int v = 0; v < 5; ++v) fzp[v] = fz[v];
             }
             if (!full) break;
+            // lean form: every thread has read the fluxes of plane k - 1 before any
+            // thread overwrites them with those of plane k
+            if constexpr (kLean) __syncthreads();
             if constexpr (kFence) __builtin_amdgcn_sched_barrier(0);
             // ---- x face (low face of the cell): (rho, vx, vy, vz, p, By, Bz)
             if (xneed) {
@@ -522,17 +589,19 @@ struct FluxTile {
             }
             __syncthreads();
             // ---- the x/y part of this cell's flux divergence, carried to the next pass
-            if (live) {
+            if constexpr (!kLean) {
+                if (live) {
     #pragma clang fp contract(off)
     #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const R fx = (lds.hx[v][row][lane + 1] - lds.hx[v][row][lane]) * idx;
-                    const R fy = (lds.hy[v][row + 1][lane] - lds.hy[v][row][lane]) * idy;
-                    acc[v] = fx + fy;
+                    for (int v = 0; v < 4; ++v) {
+                        const R fx = (lds.hx[v][row][lane + 1] - lds.hx[v][row][lane]) * idx;
+                        const R fy = (lds.hy[v][row + 1][lane] - lds.hy[v][row][lane]) * idy;
+                        acc[v] = fx + fy;
+                    }
+                    const double fx = ((double)lds.hx[4][row][lane + 1] - (double)lds.hx[4][row][lane]) * g.inv_dx[0];
+                    const double fy = ((double)lds.hy[4][row + 1][lane] - (double)lds.hy[4][row][lane]) * g.inv_dx[1];
+                    accE = fx + fy;
                 }
-                const double fx = ((double)lds.hx[4][row][lane + 1] - (double)lds.hx[4][row][lane]) * g.inv_dx[0];
-                const double fy = ((double)lds.hy[4][row + 1][lane] - (double)lds.hy[4][row][lane]) * g.inv_dx[1];
-                accE = fx + fy;
             }
             // no barrier here: the next plane's staging writes only the primitives, which
             // every thread finished reading before the barrier above, and the fluxes are

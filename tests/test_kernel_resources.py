@@ -2,10 +2,10 @@
 compiler's resource report for gfx950 (host only: hipcc cross-compiles, no GPU needed).
 
 These are performance assumptions of the kernel design, not correctness: the FP64 PPM +
-HLLD flux/update kernel runs two waves per SIMD without spilling (two workgroups'
-memory within the CU's 160 KiB), every FP32 flux/update kernel four, the FP64 HLLE and
-donor-cell ones three, the FP64 time-step CT kernel three, and no MHD stage kernel
-spills.  A different compiler can move them without changing any result; a
+HLLD flux/update kernel runs three waves per SIMD (three workgroups' memory within the
+CU's 160 KiB) with at most a few loop-invariant dwords spilled, every FP32 flux/update
+kernel four, the FP64 HLLE and donor-cell ones three, the FP64 time-step CT kernel
+three, and no other MHD stage kernel spills.  A different compiler can move them without changing any result; a
 failure names the budget that moved.
 """
 import re
@@ -56,12 +56,13 @@ CT_CFL_F64 = "_ZN3mhd11k_ct_updateILb1ELb0EdLi4EE"
 
 
 @pytest.mark.parametrize("name", FLUX_PPM_HLLD_F64)
-def test_fp64_ppm_flux_kernel_runs_two_waves_without_spills(fused, name):
+def test_fp64_ppm_flux_kernel_runs_three_waves(fused, name):
     k = _one(fused, name)
-    assert k["VGPRs"] + k.get("AGPRs", 0) <= 256, k
-    assert 2 * k["LDS Size"] <= LDS_PER_CU, k
-    assert k["Occupancy"] >= 2, k
-    assert k["ScratchSize"] == 0, k
+    assert k["VGPRs"] + k.get("AGPRs", 0) <= 168, k
+    assert 3 * k["LDS Size"] <= LDS_PER_CU, k
+    assert k["Occupancy"] >= 3, k
+    # a few loop-invariant values reloaded once per plane (measured 24 bytes per lane)
+    assert k["ScratchSize"] <= 32, k
 
 
 def test_fp64_time_step_ct_kernel_runs_three_waves(fused):

@@ -85,7 +85,8 @@ struct BatchCt {
 };
 
 template <int RECON, int RS, bool IN, class R, int SHAPE>
-__global__ __launch_bounds__(kFluxThreads) void k_flux3_batch(const BlockDesc* __restrict__ blk,
+__global__ __launch_bounds__(kFluxThreads) __attribute__((amdgpu_waves_per_eu(FluxWaves<RECON, RS, R>::min)))
+void k_flux3_batch(const BlockDesc* __restrict__ blk,
                                                              const WorkItem* __restrict__ items, int nitems,
                                                              unsigned long long* ctr, unsigned long long base,
                                                              MhdParams P, BatchCt a, R* F, R* Rc)

@@ -25,17 +25,6 @@ constexpr int TY = 4;    // rows (FP64 CT kernel that reduces the time step)
 constexpr int TY2 = 8;   // rows (other CT kernels)
 }  // namespace
 
-// Occupancy requests (waves per SIMD): four for every FP32 kernel (at most 128
-// registers), two for the FP64 PLM + HLLD kernel, three for the other FP64 kernels.
-// The FP64 PPM kernels reach three (168 registers) only in their reload form (see
-// FluxTile::kLean): the carried form held to three spilled about 36 dwords per lane and
-// ran 20 % slower (3.48 against 2.91 ms per corrector launch at 256^3), the reload form
-// spills six loop-invariant dwords and runs 2.51 against 2.67 ms.
-template <int RECON, int RS, class R>
-struct FluxWaves {
-    static constexpr int min = sizeof(R) == 4 ? 4 : (RS == 1 && RECON == 1 ? 2 : 3);
-};
-
 template <int RECON, int RS, bool IN, class R>
 __global__ __launch_bounds__(TXF* TYF) __attribute__((amdgpu_waves_per_eu(FluxWaves<RECON, RS, R>::min)))
 void k_flux3(Geo g, MhdParams P, StageArgs<R> a, int kz, unsigned int ntx, unsigned int nty, unsigned int nblk)

@@ -84,8 +84,19 @@ struct BatchCt {
     double* partial;      // per item (CFL)
 };
 
+// Waves per SIMD a batch flux kernel asks for: the single-grid request, or fewer where
+// the tile shape's LDS leaves room for fewer workgroups per CU (one workgroup of four
+// waves per CU is one wave per SIMD).
+template <int RECON, int RS, class R, int SHAPE>
+struct BatchFluxWaves {
+    static constexpr int TX = SHAPE == 0 ? 64 : (SHAPE == 1 ? 32 : 16);
+    static constexpr int lds_fit =
+        (int)(160 * 1024 / (sizeof(typename FluxTile<RECON, RS, true, R, TX, kFluxThreads / TX>::Lds) + 64));
+    static constexpr int min = lds_fit < FluxWaves<RECON, RS, R>::min ? lds_fit : FluxWaves<RECON, RS, R>::min;
+};
+
 template <int RECON, int RS, bool IN, class R, int SHAPE>
-__global__ __launch_bounds__(kFluxThreads) __attribute__((amdgpu_waves_per_eu(FluxWaves<RECON, RS, R>::min)))
+__global__ __launch_bounds__(kFluxThreads) __attribute__((amdgpu_waves_per_eu(BatchFluxWaves<RECON, RS, R, SHAPE>::min)))
 void k_flux3_batch(const BlockDesc* __restrict__ blk,
                                                              const WorkItem* __restrict__ items, int nitems,
                                                              unsigned long long* ctr, unsigned long long base,

@@ -104,6 +104,55 @@ def test_ppm_fourth_order_interface_on_cubic():
     assert np.allclose(aR[f], exact, rtol=0, atol=1e-12)
 
 
+def test_ppm_parabolas_monotone_on_monotone_data():
+    """Colella & Woodward's monotonisation (Sec. "Reconstruction and Riemann Solvers",
+    PPM): on monotone data every cell's limited parabola (edge values a_-, a_+ around
+    the average a) is monotone across the cell, i.e. its extremum is not inside it:
+    |6 (a - (a_- + a_+)/2)| <= |a_+ - a_-|.  Random monotone rows with jumps, so that
+    both one-sided corrections are active somewhere."""
+    rng = np.random.default_rng(11)
+    active = 0
+    for trial in range(40):
+        steps = rng.random(80) ** 4 * (10.0 ** rng.uniform(-2, 1, 80))
+        a = np.cumsum(steps)
+        aL, aR = oracle.recon_line("ppm", a)
+        for c in range(6, 70):
+            lo, hi = aR[c], aL[c + 1]  # cell c's edge values
+            da = hi - lo
+            a6 = 6.0 * (a[c] - 0.5 * (lo + hi))
+            tol = 1e-12 * (abs(a[c]) + 1.0)
+            assert abs(a6) <= abs(da) + 6 * tol, (trial, c, lo, a[c], hi)
+            assert min(a[c - 1], a[c]) - tol <= lo <= max(a[c - 1], a[c]) + tol
+            assert min(a[c], a[c + 1]) - tol <= hi <= max(a[c], a[c + 1]) + tol
+            active += abs(abs(a6) - abs(da)) <= 6 * tol and da != 0.0
+    assert active > 20  # the corrections were exercised (parabola ends flat at an edge)
+
+
+def test_ppm_continuous_across_its_branches():
+    """The PPM face states are a continuous, piecewise-linear function of the cell
+    averages: every branch of the slope limiter and of the monotonisation meets its
+    neighbour where they switch (at a tie both choices give the same parabola), so
+    along any straight line through data space the states move by at most a bounded
+    multiple of the step.  A jump anywhere along the scans means two branches that
+    disagree at their common boundary; the scans are checked to cross many branch
+    boundaries (kinks)."""
+    rng = np.random.default_rng(5)
+    n, m = 24, 1500
+    kinks = 0
+    for trial in range(12):
+        a0 = np.cumsum(rng.standard_normal(n)) * 0.5
+        d = rng.standard_normal(n)
+        d /= np.abs(d).max()
+        ts = np.linspace(0.0, 3.0, m + 1)
+        h = ts[1] - ts[0]
+        outs = np.array([np.concatenate(oracle.recon_line("ppm", a0 + t * d)) for t in ts])
+        diff = np.abs(np.diff(outs, axis=0))
+        assert diff.max() <= 40.0 * h, (trial, diff.max() / h)
+        second = np.abs(np.diff(outs, 2, axis=0))
+        kinks += int((second > 1e-9).sum())
+    assert kinks > 100
+
+
 @pytest.mark.parametrize("recon", ["plm", "ppm"])
 def test_recon_bounded_and_flat_at_extrema(recon):
     rng = np.random.default_rng(3)

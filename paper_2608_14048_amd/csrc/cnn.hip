@@ -248,16 +248,18 @@ __global__ __launch_bounds__(kThreads) void k_conv_lds(Geo g, const bf16_t* __re
     const int z0 = (int)(b / (ntx * nty)) * kTileZ;
     const unsigned int n = (unsigned int)g.n;
 
-    // stage the input block with its halo (periodic), 8 bytes per load
-    constexpr int CH = CINP / 4;
+    // stage the input block with its halo (periodic), 16 bytes per load (two 8-byte LDS
+    // writes: the padded LDS rows are 8-byte aligned only)
+    constexpr int CH = CINP / 8;
     for (int q = threadIdx.x; q < kHalo * CH; q += kThreads) {
         const int vq = q / CH, part = q - vq * CH;
         const int lx = vq % 18, ly = (vq / 18) % (kTileY + 2), lz = vq / (18 * (kTileY + 2));
         const unsigned int gv = ((unsigned int)wrap1(z0 + lz - 1, g.nz) * (unsigned int)g.ny +
                                  (unsigned int)wrap1(y0 + ly - 1, g.ny)) * (unsigned int)g.nx +
                                 (unsigned int)wrap1(x0 + lx - 1, g.nx);
-        *reinterpret_cast<uint2*>(&sA[lz][ly][lx][part * 4]) =
-            *reinterpret_cast<const uint2*>(X + (size_t)gv * CINP + part * 4);
+        const uint4 v = *reinterpret_cast<const uint4*>(X + (size_t)gv * CINP + part * 8);
+        *reinterpret_cast<uint2*>(&sA[lz][ly][lx][part * 8]) = uint2{v.x, v.y};
+        *reinterpret_cast<uint2*>(&sA[lz][ly][lx][part * 8 + 4]) = uint2{v.z, v.w};
     }
     __syncthreads();
 
@@ -268,26 +270,43 @@ __global__ __launch_bounds__(kThreads) void k_conv_lds(Geo g, const bf16_t* __re
     for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int t = 0; t < 27; ++t) {
-        const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
-        if constexpr (CINP % 32 == 0) {
-            const int lk8 = (lane >> 4) * 8;
+    // The weight fragments of tap t + 1 are loaded while tap t multiplies: they come from
+    // L2 (a layer's weights do not fit L1), and waiting for them at every tap left the
+    // matrix cores idle most of the time.
+    if constexpr (CINP % 32 == 0) {
+        const int lk8 = (lane >> 4) * 8;
+        auto load_b = [&](int t, s8 (&bf)[CINP / 32][2]) {
 #pragma unroll
-            for (int kc = 0; kc < CINP / 32; ++kc) {
-                s8 bf[2];
+            for (int kc = 0; kc < CINP / 32; ++kc)
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb)
-                    bf[cb] = *reinterpret_cast<const s8*>(B + ((size_t)(t * kNPad + cb * 16 + lr) * CINP + kc * 32 + lk8));
+                    bf[kc][cb] = *reinterpret_cast<const s8*>(
+                        B + ((size_t)(t * kNPad + cb * 16 + lr) * CINP + kc * 32 + lk8));
+        };
+        s8 bcur[CINP / 32][2], bnxt[CINP / 32][2];
+        load_b(0, bcur);
+        for (int t = 0; t < 27; ++t) {
+            const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+            load_b(t < 26 ? t + 1 : t, bnxt);
+#pragma unroll
+            for (int kc = 0; kc < CINP / 32; ++kc) {
 #pragma unroll
                 for (int rb = 0; rb < NRB; ++rb) {
                     // two 8-byte reads: the padded LDS rows are 8-byte aligned only
                     const bf16_t* xa = &sA[TZ * w + rb / 4 + dz + 1][rb % 4 + dy + 1][lr + dx + 1][kc * 32 + lk8];
                     const s4 alo = *reinterpret_cast<const s4*>(xa), ahi = *reinterpret_cast<const s4*>(xa + 4);
 #pragma unroll
-                    for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_k32(alo, ahi, bf[cb], acc[rb][cb]);
+                    for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma_k32(alo, ahi, bcur[kc][cb], acc[rb][cb]);
                 }
             }
-        } else {
+#pragma unroll
+            for (int kc = 0; kc < CINP / 32; ++kc)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) bcur[kc][cb] = bnxt[kc][cb];
+        }
+    } else {
+        for (int t = 0; t < 27; ++t) {
+            const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
 #pragma unroll
             for (int kc = 0; kc < CINP / 16; ++kc) {
                 s4 bf[2];
@@ -313,17 +332,24 @@ __global__ __launch_bounds__(kThreads) void k_conv_lds(Geo g, const bf16_t* __re
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
             const int nn = cb * 16 + lr;
+            if constexpr (MODE == 1) {
+                // the four voxels of a lane are consecutive: one 16-byte store
+                if (nn < nstore) {
+                    const float b = bias[nn];
+                    const float4 o4 = {acc[rb][cb][0] + b, acc[rb][cb][1] + b, acc[rb][cb][2] + b,
+                                       acc[rb][cb][3] + b};
+                    *reinterpret_cast<float4*>(O + (size_t)nn * n + vrow + lk) = o4;
+                }
+            } else {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const unsigned int v = vrow + lk + i;
-                float val = acc[rb][cb][i];
-                if (MODE == 0) {
-                    val = fmaxf(val + bias[nn], 0.f);
-                    Y[(size_t)v * kNPad + nn] = f2bf(val);
-                } else if (MODE == 1) {
-                    if (nn < nstore) O[(size_t)nn * n + v] = val + bias[nn];
-                } else {
-                    if (!(bf2f(M[(size_t)v * kNPad + nn]) > 0.f)) val = 0.f;
+                for (int i = 0; i < 4; ++i) {
+                    const unsigned int v = vrow + lk + i;
+                    float val = acc[rb][cb][i];
+                    if (MODE == 0) {
+                        val = fmaxf(val + bias[nn], 0.f);
+                    } else {
+                        if (!(bf2f(M[(size_t)v * kNPad + nn]) > 0.f)) val = 0.f;
+                    }
                     Y[(size_t)v * kNPad + nn] = f2bf(val);
                 }
             }

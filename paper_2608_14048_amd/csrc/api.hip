@@ -110,9 +110,9 @@ struct Layout {
 
 Geo make_geo(const mhd_grid* grid);
 
-// z planes per workgroup of the MHD kernels: about 3072 flux/update workgroups (six
-// rounds of the 512 that the FP64 PPM kernel keeps resident, two per CU), and at least
-// two planes per chunk.  Each chunk primes its z pipeline once (five planes for PPM),
+// z planes per workgroup of the MHD kernels: about 3072 flux/update workgroups (four
+// rounds of the 768 that the FP64 PPM kernel keeps resident, three per CU; targets of
+// 1536, 2304 and 4608 measured no faster at 256^3), and at least two planes per chunk.  Each chunk primes its z pipeline once (five planes for PPM),
 // which small grids afford: at 64^3 chunks of 2 planes took the step from 0.355 to
 // 0.192 ms against chunks of 8, with no change at 256^3.
 int choose_kz(const mhd_grid* g)

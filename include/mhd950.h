@@ -272,6 +272,43 @@ mhd_status mhd_batch_get_shapes(const mhd_batch* batch, int* shapes, int nblocks
  * pass, class-major (nout >= classes * 3).  Synchronises the stream. */
 mhd_status mhd_batch_tune(mhd_batch* batch, int reps, float* ms_out, int nout);
 
+/* ---------------------------------------------------------------------------------
+ * One periodic domain as coupled meshblocks.  The paper divides a domain into identical
+ * blocks, each padded with ghost cells that one exchange per stage fills from all its
+ * face, edge and corner neighbours (Sec. "Mesh, Coordinates, and Boundary Conditions"),
+ * and its single-device benchmark runs the 512 x 512 x 256 box in 128^3 blocks (Sec.
+ * "Single-Device Performance").
+ *
+ * mhd_batch_couple turns a batch of nblocks = nbx nby nbz FP64 blocks, all of
+ * (bx + 2 ghost) x (by + 2 ghost) x (bz + 2 ghost) cells, into the periodic domain of
+ * (nbx bx) x (nby by) x (nbz bz) cells with side lengths length[0..2]: block
+ * b = bi + nbx (bj + nby bk) holds the domain cells [bi bx, (bi+1) bx) x [bj by, ...) x
+ * [bk bz, ...) as its interior, with `ghost` layers on every side.  Every block takes the
+ * domain's spacing length[a] / (nb_a b_a).  From then on each stage of mhd_batch_step is
+ * followed on the device by the exchange: every ghost cell of every block (all 8 fields;
+ * a face field goes with the cell on its high side) is copied from the interior cell of
+ * the block that owns that domain cell; and after the last stage every block is given
+ * the one CFL step of the whole domain (the minimum over the interiors).  A block's
+ * interior then evolves bitwise as the same cells of the domain advanced as one grid
+ * with the same steps.  ghost must be at least the reconstruction's stencil plus the one
+ * cell the edge EMFs reach beyond it (donor cell 2, PLM 3, PPM 4) and at most 64;
+ * nblocks_xyz must multiply to the batch's block count; all blocks must have the same
+ * extents, larger than 2 ghost (else MHD_E_INVAL).  FP32-bulk batches are
+ * MHD_E_UNSUPPORTED.  The current state's ghost cells are refreshed and its step is put
+ * on the device; a later mhd_batch_set_state does the same.  mhd_batch_step's host dt,
+ * if given, must then be one value for all blocks (else MHD_E_INVAL).  Synchronises.
+ * --------------------------------------------------------------------------------- */
+mhd_status mhd_batch_couple(mhd_batch* batch, const int nblocks_xyz[3], int ghost, const double length[3]);
+
+/* The domain state of a coupled batch in the single-context canonical layout of the
+ * whole domain ([8][nz][ny][nx] doubles, host or device pointer as flagged).  set
+ * fills every block's interior and ghost cells from it (staging a host source through
+ * the workspace) and puts the domain's CFL step on the device; get gathers the
+ * interiors.  MHD_E_INVAL on a batch that is not coupled.  Synchronise for host
+ * buffers. */
+mhd_status mhd_batch_set_domain_state(mhd_batch* batch, const double* src, int src_is_device);
+mhd_status mhd_batch_get_domain_state(mhd_batch* batch, double* dst, int dst_is_device);
+
 void mhd_batch_destroy(mhd_batch* batch);
 
 /* ---------------------------------------------------------------------------------

@@ -10,7 +10,7 @@ this package holds the ctypes binding (``binding``) and the seeded synthetic inp
 (``inputs``).  Importing the package loads nothing; the library is opened on first
 use and its absence is an error.
 """
-from .binding import (Batch, Closure, MhdError, box_filter, Sim, load_library, make_grid, make_physics, make_scheme,  # noqa: F401
+from .binding import (Batch, Closure, Domain, MhdError, box_filter, Sim, load_library, make_grid, make_physics, make_scheme,  # noqa: F401
                       mhd_create, mhd_destroy, mhd_diagnostics, mhd_dt_cfl, mhd_get_state,
                       mhd_set_state, mhd_state_len, mhd_step, mhd_strerror, mhd_timing_enable,
                       mhd_timing_name, mhd_timing_read, mhd_workspace_bytes,

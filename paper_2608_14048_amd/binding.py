@@ -97,6 +97,9 @@ def load_library(path: str = LIB_PATH):
     L.mhd_batch_set_shapes.argtypes = [vp, ip, ctypes.c_int]
     L.mhd_batch_get_shapes.argtypes = [vp, ip, ctypes.c_int]
     L.mhd_batch_tune.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_float), ctypes.c_int]
+    L.mhd_batch_couple.argtypes = [vp, ip, ctypes.c_int, dp]
+    L.mhd_batch_set_domain_state.argtypes = [vp, vp, ctypes.c_int]
+    L.mhd_batch_get_domain_state.argtypes = [vp, vp, ctypes.c_int]
     L.mhd_batch_destroy.argtypes = [vp]
     L.mhd_batch_destroy.restype = None
     fp = ctypes.POINTER(ctypes.c_float)
@@ -124,6 +127,7 @@ def load_library(path: str = LIB_PATH):
                  "mhd_batch_create", "mhd_batch_state_len", "mhd_batch_set_state",
                  "mhd_batch_get_state", "mhd_batch_step", "mhd_batch_dt_cfl",
                  "mhd_batch_set_shapes", "mhd_batch_get_shapes", "mhd_batch_tune",
+                 "mhd_batch_couple", "mhd_batch_set_domain_state", "mhd_batch_get_domain_state",
                  "mhd_cnn_param_count", "mhd_cnn_workspace_bytes", "mhd_cnn_create", "mhd_cnn_set_params",
                  "mhd_cnn_get_params", "mhd_cnn_get_grads", "mhd_cnn_set_scales", "mhd_cnn_forward",
                  "mhd_cnn_output", "mhd_closure_apply", "mhd_cnn_zero_grad", "mhd_cnn_accumulate",
@@ -345,6 +349,22 @@ def mhd_batch_tune(b: int, reps: int, nclasses: int) -> np.ndarray:
     out = (ctypes.c_float * (3 * nclasses))()
     _check(load_library().mhd_batch_tune(ctypes.c_void_p(b), int(reps), out, 3 * nclasses), "mhd_batch_tune")
     return np.array(list(out), dtype=np.float64).reshape(nclasses, 3)
+
+
+def mhd_batch_couple(b: int, nblocks_xyz, ghost: int, length):
+    nb = (ctypes.c_int * 3)(*[int(v) for v in nblocks_xyz])
+    L = (ctypes.c_double * 3)(*[float(v) for v in length])
+    _check(load_library().mhd_batch_couple(ctypes.c_void_p(b), nb, int(ghost), L), "mhd_batch_couple")
+
+
+def mhd_batch_set_domain_state(b: int, ptr: int, is_device: bool):
+    _check(load_library().mhd_batch_set_domain_state(ctypes.c_void_p(b), ctypes.c_void_p(ptr), int(is_device)),
+           "mhd_batch_set_domain_state")
+
+
+def mhd_batch_get_domain_state(b: int, ptr: int, is_device: bool):
+    _check(load_library().mhd_batch_get_domain_state(ctypes.c_void_p(b), ctypes.c_void_p(ptr), int(is_device)),
+           "mhd_batch_get_domain_state")
 
 
 def mhd_batch_destroy(b: int):
@@ -633,6 +653,67 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Domain:
+    """One periodic domain of `shape` cells advanced as coupled meshblocks of `block`
+    cells, each stored with `ghost` layers of ghost cells that a device exchange refills
+    after every stage (a coupled Batch).  The state is the domain's canonical FP64 state;
+    every block advances by the domain's one CFL step."""
+
+    def __init__(self, shape, block, length=(1.0, 1.0, 1.0), ghost=None, physics=None, scheme=None,
+                 device="cuda:0", stream=None):
+        shape = tuple(int(v) for v in shape)
+        block = tuple(int(v) for v in block)
+        if any(s % b for s, b in zip(shape, block)):
+            raise ValueError(f"block {block} does not tile the domain {shape}")
+        scheme = dict(scheme or {})
+        if ghost is None:
+            ghost = {"dc": 2, "plm": 3, "ppm": 4}[scheme.get("recon", "plm")]
+        self.shape, self.block, self.ghost = shape, block, int(ghost)
+        self.nblocks_xyz = tuple(s // b for s, b in zip(shape, block))
+        nb = self.nblocks_xyz[0] * self.nblocks_xyz[1] * self.nblocks_xyz[2]
+        padded = tuple(b + 2 * self.ghost for b in block)
+        h = tuple(float(L) / s for L, s in zip(length, shape))
+        self.length = tuple(float(v) for v in length)
+        # the spacing is set exactly by couple(); these lengths only have to be valid
+        self.batch = Batch([padded] * nb, [tuple(p * hh for p, hh in zip(padded, h))] * nb, physics=physics,
+                           scheme=scheme, device=device, stream=stream)
+        mhd_batch_couple(self.batch.ctx, self.nblocks_xyz, self.ghost, self.length)
+        self.n = 8 * shape[0] * shape[1] * shape[2]
+
+    def set_state(self, state):
+        import torch
+        if isinstance(state, torch.Tensor) and state.is_cuda:
+            t = state.detach().to(torch.float64).contiguous().reshape(-1)
+            assert t.numel() == self.n, (t.numel(), self.n)
+            mhd_batch_set_domain_state(self.batch.ctx, t.data_ptr(), True)
+            torch.cuda.current_stream(t.device).synchronize()
+        else:
+            a = np.ascontiguousarray(np.asarray(state, dtype=np.float64).reshape(-1))
+            assert a.size == self.n, (a.size, self.n)
+            mhd_batch_set_domain_state(self.batch.ctx, a.ctypes.data, False)
+
+    def state(self, device: bool = False):
+        import torch
+        if device:
+            out = torch.empty(self.n, dtype=torch.float64, device=self.batch.device)
+            mhd_batch_get_domain_state(self.batch.ctx, out.data_ptr(), True)
+            return out
+        a = np.empty(self.n, dtype=np.float64)
+        mhd_batch_get_domain_state(self.batch.ctx, a.ctypes.data, False)
+        return a
+
+    def step(self, dt=None):
+        """Advance by dt (every block alike) or, with None, by the domain's CFL step
+        already on the device."""
+        self.batch.step(None if dt is None else [float(dt)] * self.batch.nb)
+
+    def dt_cfl(self) -> float:
+        return float(self.batch.dt_cfl()[0])
+
+    def close(self):
+        self.batch.close()
 
 
 class Closure:

@@ -174,6 +174,76 @@ __global__ __launch_bounds__(256) void k_block_min(const double* __restrict__ pa
     if (threadIdx.x == 0) dt[b] = scale * min_nan(min_nan(sm[0], sm[1]), min_nan(sm[2], sm[3]));
 }
 
+// ----------------------------------------------------------------------------------
+// coupled blocks of one periodic domain
+// ----------------------------------------------------------------------------------
+
+// Block b = (bi, bj, bk), x fastest, holds the domain cells [bi bs0, (bi + 1) bs0) x ...
+// as its interior, padded by g ghost cells on every side (padded extents pn).
+struct DomainMap {
+    int nb[3], bs[3], pn[3], dn[3];  // blocks, interior cells, padded cells, domain cells
+    int g;
+    long long pc;                    // cells of a padded block
+    long long dcells;                // cells of the domain
+};
+
+// i taken periodically into [0, n) (couple() keeps n >= the ghost width, so one wrap
+// suffices; the full modulo keeps every index in range regardless).
+__device__ __forceinline__ int dwrap(int i, int n)
+{
+    const int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+// MODE 0: every block's ghost cells from the blocks that own those domain cells (all 8
+// fields; a face field travels with the cell on its high side).  MODE 1: every padded
+// cell from the domain state dom ([8][NZ][NY][NX]).  MODE 2: the interior cells into
+// dom.  reg: the FP64 register, block b's 8 fields of pc cells at reg + 8 off[b].
+template <int MODE>
+__global__ __launch_bounds__(256) void k_domain_copy(DomainMap m, const unsigned long long* __restrict__ off,
+                                                     int nblocks, double* reg, double* dom)
+{
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= m.pc * nblocks) return;
+    const int b = (int)(t / m.pc);
+    const long long c = t - (long long)b * m.pc;
+    const int i = (int)(c % m.pn[0]), j = (int)((c / m.pn[0]) % m.pn[1]), k = (int)(c / ((long long)m.pn[0] * m.pn[1]));
+    const bool interior = i >= m.g && i < m.g + m.bs[0] && j >= m.g && j < m.g + m.bs[1] && k >= m.g &&
+                          k < m.g + m.bs[2];
+    if (MODE == 0 && interior) return;
+    if (MODE == 2 && !interior) return;
+    const int bi = b % m.nb[0], bj = (b / m.nb[0]) % m.nb[1], bk = b / (m.nb[0] * m.nb[1]);
+    // the domain cell (taken periodically)
+    const int I = dwrap(bi * m.bs[0] + i - m.g, m.dn[0]);
+    const int J = dwrap(bj * m.bs[1] + j - m.g, m.dn[1]);
+    const int K = dwrap(bk * m.bs[2] + k - m.g, m.dn[2]);
+    double* blk = reg + off[b] * 8ULL;
+    if constexpr (MODE == 0) {
+        const int oi = I / m.bs[0], oj = J / m.bs[1], ok = K / m.bs[2];
+        const int ob = (ok * m.nb[1] + oj) * m.nb[0] + oi;
+        const long long oc = ((long long)(K - ok * m.bs[2] + m.g) * m.pn[1] + (J - oj * m.bs[1] + m.g)) * m.pn[0] +
+                             (I - oi * m.bs[0] + m.g);
+        const double* src = reg + off[ob] * 8ULL;
+#pragma unroll
+        for (int f = 0; f < 8; ++f) blk[f * m.pc + c] = src[f * m.pc + oc];
+    } else {
+        const long long dc = ((long long)K * m.dn[1] + J) * m.dn[0] + I;
+        if constexpr (MODE == 1) {
+#pragma unroll
+            for (int f = 0; f < 8; ++f) blk[f * m.pc + c] = dom[f * m.dcells + dc];
+        } else {
+#pragma unroll
+            for (int f = 0; f < 8; ++f) dom[f * m.dcells + dc] = blk[f * m.pc + c];
+        }
+    }
+}
+
+// dt[1 .. n) = dt[0]: every block of a coupled domain takes the domain's step.
+__global__ void k_dt_broadcast(double* dt, int n)
+{
+    for (int b = 1 + (int)threadIdx.x; b < n; b += (int)blockDim.x) dt[b] = dt[0];
+}
+
 }  // namespace mhd
 
 // ----------------------------------------------------------------------------------
@@ -212,6 +282,10 @@ struct mhd_batch {
     unsigned long long base[2];
     int cur;
     double cfl_scale;
+    // coupled blocks of one periodic domain (mhd_batch_couple)
+    bool coupled = false;
+    DomainMap dom;
+    unsigned long long* d_off = nullptr;  // block offsets (cells) on the device
 };
 
 namespace {
@@ -219,7 +293,7 @@ namespace {
 size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct BLayout {
-    size_t reg, F, Rc, partial, dt, ctr, blk, fitems, citems, cstart, clist, total;
+    size_t reg, F, Rc, partial, dt, ctr, blk, offs, fitems, citems, cstart, clist, total;
     unsigned long long ncell;
     int cap_f, cap_c;
     std::vector<unsigned long long> off;
@@ -292,16 +366,19 @@ BLayout blayout(int nb, const mhd_grid* grids, const mhd_scheme* s)
     L.reg = a256((size_t)o * register_bytes(1, fp32));
     L.F = a256(std::max((size_t)o * NFACE * rsz, (size_t)o * 8 * sizeof(double)));
     L.Rc = a256((size_t)o * 3 * rsz);
-    L.partial = a256((size_t)std::max(cc, maxblk) * sizeof(double));
+    // CFL partials: one per CT item, per workgroup of a block's own reduction, or per
+    // workgroup of the reduction over all blocks' cells (a coupled domain)
+    L.partial = a256((size_t)std::max({cc, maxblk, (long long)blocks_for((long long)o)}) * sizeof(double));
     L.dt = a256((size_t)nb * sizeof(double));
     L.ctr = a256(2 * sizeof(unsigned long long));
     L.blk = a256((size_t)nb * sizeof(BlockDesc));
+    L.offs = a256((size_t)nb * sizeof(unsigned long long));
     L.fitems = a256((size_t)cf * sizeof(WorkItem));
     L.citems = a256((size_t)cc * sizeof(WorkItem));
     L.cstart = a256((size_t)(nb + 1) * sizeof(int));
     L.clist = a256((size_t)cc * sizeof(int));
-    L.total = 3 * L.reg + L.F + L.Rc + L.partial + L.dt + L.ctr + L.blk + L.fitems + L.citems + L.cstart +
-              L.clist;
+    L.total = 3 * L.reg + L.F + L.Rc + L.partial + L.dt + L.ctr + L.blk + L.offs + L.fitems + L.citems +
+              L.cstart + L.clist;
     return L;
 }
 
@@ -475,28 +552,61 @@ mhd_status bstage(mhd_batch* c, int recon, char* in, char* base, char* out, doub
     return bdev(e);
 }
 
+// The CFL step of a coupled domain (the minimum over every block's interior) into every
+// dt[b].
+hipError_t domain_cfl(mhd_batch* c, const char* reg)
+{
+    const DomainMap& m = c->dom;
+    hipError_t e = launch_cfl_blocks(c->geo[0], c->mp, (const double*)reg, c->d_off, c->nb, m.g, m.bs[0], m.bs[1],
+                                     m.bs[2], c->partial, c->dt, c->cfl_scale, c->stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dt_broadcast, dim3(1), dim3(256), 0, c->stream, c->dt, c->nb);
+    return hipGetLastError();
+}
+
+// After a stage of a coupled domain: every block's ghost cells of the stage's output
+// from their owners (one exchange per stage, Sec. "Mesh, Coordinates, and Boundary
+// Conditions"); after the last stage also the domain's CFL step.
+mhd_status domain_after_stage(mhd_batch* c, char* out, bool last)
+{
+    const long long tot = c->dom.pc * c->nb;
+    hipLaunchKernelGGL(k_domain_copy<0>, dim3((unsigned int)((tot + 255) / 256)), dim3(256), 0, c->stream, c->dom,
+                       c->d_off, c->nb, (double*)out, (double*)nullptr);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && last) e = domain_cfl(c, out);
+    return bdev(e);
+}
+
 mhd_status bstep(mhd_batch* c)
 {
     const int s0 = c->cur, s1 = (c->cur + 1) % 3, s2 = (c->cur + 2) % 3;
     char* S = c->reg[s0];
     char* A = c->reg[s1];
     char* B = c->reg[s2];
+    // a coupled domain takes its time step after the exchange, not from the blocks'
+    // padded cells (their outer ghost layers are not updated correctly)
+    const bool cp = c->coupled;
     mhd_status st;
     switch (c->scheme.integ) {
     case MHD_INT_VL2:
         st = bstage(c, MHD_RECON_DC, S, S, A, 0.0, 1.0, 0.5, false);
+        if (st == MHD_OK && cp) st = domain_after_stage(c, A, false);
         if (st != MHD_OK) return st;
-        st = bstage(c, c->scheme.recon, A, S, B, 0.0, 1.0, 1.0, true);
+        st = bstage(c, c->scheme.recon, A, S, B, 0.0, 1.0, 1.0, !cp);
+        if (st == MHD_OK && cp) st = domain_after_stage(c, B, true);
         c->cur = s2;
         return st;
     case MHD_INT_RK2:
         st = bstage(c, c->scheme.recon, S, S, A, 0.0, 1.0, 1.0, false);
+        if (st == MHD_OK && cp) st = domain_after_stage(c, A, false);
         if (st != MHD_OK) return st;
-        st = bstage(c, c->scheme.recon, A, S, B, 0.5, 0.5, 0.5, true);
+        st = bstage(c, c->scheme.recon, A, S, B, 0.5, 0.5, 0.5, !cp);
+        if (st == MHD_OK && cp) st = domain_after_stage(c, B, true);
         c->cur = s2;
         return st;
     default:
-        st = bstage(c, c->scheme.recon, S, S, A, 0.0, 1.0, 1.0, true);
+        st = bstage(c, c->scheme.recon, S, S, A, 0.0, 1.0, 1.0, !cp);
+        if (st == MHD_OK && cp) st = domain_after_stage(c, A, true);
         c->cur = s1;
         return st;
     }
@@ -590,6 +700,7 @@ mhd_status mhd_batch_create(int nblocks, const mhd_grid* grids, const mhd_physic
     c->dt = (double*)p; p += L.dt;
     c->ctr = (unsigned long long*)p; p += L.ctr;
     c->d_blk = (BlockDesc*)p; p += L.blk;
+    c->d_off = (unsigned long long*)p; p += L.offs;
     c->d_fitems = (WorkItem*)p; p += L.fitems;
     c->d_citems = (WorkItem*)p; p += L.citems;
     c->d_cstart = (int*)p; p += L.cstart;
@@ -601,6 +712,9 @@ mhd_status mhd_batch_create(int nblocks, const mhd_grid* grids, const mhd_physic
     hipError_t e = hipMemcpyAsync(c->ctr, zero, sizeof(zero), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d_blk, desc.data(), desc.size() * sizeof(BlockDesc), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->d_off, L.off.data(), L.off.size() * sizeof(unsigned long long), hipMemcpyHostToDevice,
+                           c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     st = e == hipSuccess ? build_all(c) : MHD_E_DEVICE;
     if (st != MHD_OK) {
@@ -640,6 +754,7 @@ mhd_status mhd_batch_set_state(mhd_batch* c, const double* src, int src_is_devic
         if (e == hipSuccess && c->fp32)
             e = launch_pack_fp32(c->geo[b], canon, c->reg[c->cur] + c->off[b] * (unsigned long long)c->reg_bpc, c->stream);
     }
+    if (e == hipSuccess && c->coupled) return domain_after_stage(c, c->reg[c->cur], true);
     return bdev(e);
 }
 
@@ -664,8 +779,10 @@ mhd_status mhd_batch_step(mhd_batch* c, const double* dt)
 {
     if (!c) return MHD_E_INVAL;
     if (dt) {
-        for (int b = 0; b < c->nb; ++b)
+        for (int b = 0; b < c->nb; ++b) {
             if (!(dt[b] > 0.0) || !std::isfinite(dt[b])) return MHD_E_INVAL;
+            if (c->coupled && dt[b] != dt[0]) return MHD_E_INVAL;  // one domain, one step
+        }
         hipError_t e = hipMemcpyAsync(c->dt, dt, (size_t)c->nb * sizeof(double), hipMemcpyHostToDevice, c->stream);
         if (e != hipSuccess) return MHD_E_DEVICE;
     }
@@ -785,6 +902,91 @@ mhd_status mhd_batch_tune(mhd_batch* c, int reps, float* ms_out, int nout)
     }
     c->shape = cands[pick];
     return build_all(c);
+}
+
+mhd_status mhd_batch_couple(mhd_batch* c, const int nblocks_xyz[3], int ghost, const double length[3])
+{
+    if (!c || !nblocks_xyz || !length) return MHD_E_INVAL;
+    if (c->fp32) return MHD_E_UNSUPPORTED;
+    // the reconstruction's stencil plus the one cell the edge EMFs reach beyond it
+    const int need = c->scheme.recon == MHD_RECON_PPM ? 4 : (c->scheme.recon == MHD_RECON_PLM ? 3 : 2);
+    if (ghost < need || ghost > 64) return MHD_E_INVAL;
+    long long nbt = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (nblocks_xyz[a] < 1 || nblocks_xyz[a] > 4096) return MHD_E_INVAL;
+        if (!(length[a] > 0.0) || !std::isfinite(length[a])) return MHD_E_INVAL;
+        nbt *= nblocks_xyz[a];
+    }
+    if (nbt != c->nb) return MHD_E_INVAL;
+    const Geo& g0 = c->geo[0];
+    const int pn[3] = {g0.nx, g0.ny, g0.nz};
+    for (int b = 1; b < c->nb; ++b)
+        if (c->geo[b].nx != pn[0] || c->geo[b].ny != pn[1] || c->geo[b].nz != pn[2]) return MHD_E_INVAL;
+    DomainMap m;
+    m.g = ghost;
+    for (int a = 0; a < 3; ++a) {
+        m.nb[a] = nblocks_xyz[a];
+        m.pn[a] = pn[a];
+        m.bs[a] = pn[a] - 2 * ghost;
+        if (m.bs[a] < 1) return MHD_E_INVAL;
+        m.dn[a] = m.nb[a] * m.bs[a];
+        if (m.dn[a] < ghost) return MHD_E_INVAL;  // a ghost layer must map onto distinct domain cells
+    }
+    m.pc = (long long)pn[0] * pn[1] * pn[2];
+    m.dcells = (long long)m.dn[0] * m.dn[1] * m.dn[2];
+    // every block takes the domain's spacing, as a single grid of the domain does
+    std::vector<BlockDesc> desc(c->nb);
+    for (int b = 0; b < c->nb; ++b) {
+        for (int a = 0; a < 3; ++a) {
+            c->geo[b].dx[a] = length[a] / m.dn[a];
+            c->geo[b].inv_dx[a] = 1.0 / c->geo[b].dx[a];
+        }
+        desc[b] = BlockDesc{c->geo[b], c->off[b]};
+    }
+    hipError_t e = hipMemcpyAsync(c->d_blk, desc.data(), desc.size() * sizeof(BlockDesc), hipMemcpyHostToDevice,
+                                  c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return MHD_E_DEVICE;
+    c->dom = m;
+    c->coupled = true;
+    // the current state: ghosts from their owners, and the domain's step
+    return domain_after_stage(c, c->reg[c->cur], true);
+}
+
+mhd_status mhd_batch_set_domain_state(mhd_batch* c, const double* src, int src_is_device)
+{
+    if (!c || !src || !c->coupled) return MHD_E_INVAL;
+    const size_t nbytes = (size_t)c->dom.dcells * 8 * sizeof(double);
+    const double* d = src;
+    hipError_t e = hipSuccess;
+    if (!src_is_device) {
+        // staged through the face-flux area, which holds at least 8 doubles per cell
+        e = hipMemcpyAsync(c->F, src, nbytes, hipMemcpyHostToDevice, c->stream);
+        d = (const double*)c->F;
+    }
+    const long long tot = c->dom.pc * c->nb;
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_domain_copy<1>, dim3((unsigned int)((tot + 255) / 256)), dim3(256), 0, c->stream, c->dom,
+                           c->d_off, c->nb, (double*)c->reg[c->cur], const_cast<double*>(d));
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = domain_cfl(c, c->reg[c->cur]);
+    if (e == hipSuccess && !src_is_device) e = hipStreamSynchronize(c->stream);
+    return bdev(e);
+}
+
+mhd_status mhd_batch_get_domain_state(mhd_batch* c, double* dst, int dst_is_device)
+{
+    if (!c || !dst || !c->coupled) return MHD_E_INVAL;
+    const size_t nbytes = (size_t)c->dom.dcells * 8 * sizeof(double);
+    double* d = dst_is_device ? dst : (double*)c->F;
+    const long long tot = c->dom.pc * c->nb;
+    hipLaunchKernelGGL(k_domain_copy<2>, dim3((unsigned int)((tot + 255) / 256)), dim3(256), 0, c->stream, c->dom,
+                       c->d_off, c->nb, (double*)c->reg[c->cur], d);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && !dst_is_device) e = hipMemcpyAsync(dst, c->F, nbytes, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && !dst_is_device) e = hipStreamSynchronize(c->stream);
+    return bdev(e);
 }
 
 void mhd_batch_destroy(mhd_batch* c) { delete c; }

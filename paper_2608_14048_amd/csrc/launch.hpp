@@ -86,6 +86,12 @@ hipError_t launch_unpack_fp32(const Geo& g, const void* reg, double* canon, hipS
 // partial: ceil(n/kBlock) doubles; dt_out: 1 double on the device.
 hipError_t launch_cfl_mhd(const Geo& g, const MhdParams& p, const double* U, double* partial,
                           double* dt_out, double scale, hipStream_t s);
+// The same over the interior cells of nb equal padded FP64 blocks of grid pg (ghost
+// layers on every side, interior bx x by x bz, block b's register at reg + 8 off[b]
+// doubles); partial: ceil(nb bx by bz / kBlock) doubles.
+hipError_t launch_cfl_blocks(const Geo& pg, const MhdParams& p, const double* reg, const unsigned long long* off,
+                             int nb, int ghost, int bx, int by, int bz, double* partial, double* dt_out,
+                             double scale, hipStream_t s);
 hipError_t launch_cfl_dust(const Geo& g, const DustParams& p, const double* U,
                            double* partial, double* dt_out, double scale, hipStream_t s);
 // out[0] = scale * (NaN-propagating) min of partial[0..m)

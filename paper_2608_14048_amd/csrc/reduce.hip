@@ -44,35 +44,65 @@ __device__ __forceinline__ double block_min(double v)
     return r;
 }
 
-// The same arithmetic, rounded as written, as the time step the last stage of a step
-// reduces (mhd_tiles.hpp), so a state gives the same bits whichever kernel takes its step.
+// Time step of eq. (cfl) of cell c of a grid of n cells; cx, cy, cz: the cells whose
+// low faces are c's high faces.  The same arithmetic, rounded as written, as the time
+// step the last stage of a step reduces (mhd_tiles.hpp), so a state gives the same bits
+// whichever kernel takes its step.
+__device__ __forceinline__ double cfl_cell(const Geo& g, const MhdParams& p, const double* __restrict__ U,
+                                           long long n, long long c, long long cx, long long cy, long long cz)
+{
+#pragma clang fp contract(off)
+    const double bx = 0.5 * (U[5 * n + c] + U[5 * n + cx]);
+    const double by = 0.5 * (U[6 * n + c] + U[6 * n + cy]);
+    const double bz = 0.5 * (U[7 * n + c] + U[7 * n + cz]);
+    double d = U[c];
+    if (d < p.rho_floor) d = p.rho_floor;
+    const double id = rcp(d);
+    const double v[3] = {U[n + c] * id, U[2 * n + c] * id, U[3 * n + c] * id};
+    const double ke = 0.5 * d * ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+    const double b2 = (bx * bx + by * by) + bz * bz;
+    double pr = (p.gamma - 1.0) * ((U[4 * n + c] - ke) - 0.5 * b2);
+    if (pr < p.p_floor) pr = p.p_floor;
+    const double bd[3] = {bx, by, bz};
+    double r = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double cf = fast_speed(p.gamma, d, pr, b2, bd[a]);
+        r = min_nan(r, div_r(g.dx[a], fabs(v[a]) + cf));
+    }
+    return r;
+}
+
 __global__ __launch_bounds__(kBlock) void k_cfl_mhd(Geo g, MhdParams p, const double* __restrict__ U,
                                                     double* __restrict__ partial)
 {
-#pragma clang fp contract(off)
     const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
     double r = INFINITY;
     if (c < g.n) {
         int i, j, k;
         cell_ijk(g, c, i, j, k);
-        const long long n = g.n;
-        const double bx = 0.5 * (U[5 * n + c] + U[5 * n + shifted(g, i, j, k, 0, 1)]);
-        const double by = 0.5 * (U[6 * n + c] + U[6 * n + shifted(g, i, j, k, 1, 1)]);
-        const double bz = 0.5 * (U[7 * n + c] + U[7 * n + shifted(g, i, j, k, 2, 1)]);
-        double d = U[c];
-        if (d < p.rho_floor) d = p.rho_floor;
-        const double id = rcp(d);
-        const double v[3] = {U[n + c] * id, U[2 * n + c] * id, U[3 * n + c] * id};
-        const double ke = 0.5 * d * ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
-        const double b2 = (bx * bx + by * by) + bz * bz;
-        double pr = (p.gamma - 1.0) * ((U[4 * n + c] - ke) - 0.5 * b2);
-        if (pr < p.p_floor) pr = p.p_floor;
-        const double bd[3] = {bx, by, bz};
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const double cf = fast_speed(p.gamma, d, pr, b2, bd[a]);
-            r = min_nan(r, div_r(g.dx[a], fabs(v[a]) + cf));
-        }
+        r = cfl_cell(g, p, U, g.n, c, shifted(g, i, j, k, 0, 1), shifted(g, i, j, k, 1, 1), shifted(g, i, j, k, 2, 1));
+    }
+    r = block_min(r);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+// The time step over the interior cells of nb equal padded blocks (grid pg each, g
+// ghost layers, interior bx x by x bz; block b's register at reg + 8 off[b] doubles):
+// ghost cells are left out (the outermost layer's high neighbours are not in the block).
+__global__ __launch_bounds__(kBlock) void k_cfl_blocks(Geo pg, MhdParams p, const double* __restrict__ reg,
+                                                       const unsigned long long* __restrict__ off, int nb, int gh,
+                                                       int bx, int by, int bz, double* __restrict__ partial)
+{
+    const long long per = (long long)bx * by * bz;
+    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+    double r = INFINITY;
+    if (t < per * nb) {
+        const int b = (int)(t / per);
+        const long long q = t - (long long)b * per;
+        const int i = (int)(q % bx) + gh, j = (int)((q / bx) % by) + gh, k = (int)(q / ((long long)bx * by)) + gh;
+        const long long c = ((long long)k * pg.ny + j) * pg.nx + i;
+        r = cfl_cell(pg, p, reg + off[b] * 8ULL, pg.n, c, c + 1, c + pg.nx, c + (long long)pg.nx * pg.ny);
     }
     r = block_min(r);
     if (threadIdx.x == 0) partial[blockIdx.x] = r;
@@ -128,6 +158,17 @@ hipError_t launch_cfl_mhd(const Geo& g, const MhdParams& p, const double* U, dou
     const unsigned int nb = blocks_for(g.n);
     hipLaunchKernelGGL(k_cfl_mhd, dim3(nb), dim3(kBlock), 0, s, g, p, U, partial);
     hipLaunchKernelGGL(k_min_final, dim3(1), dim3(kBlock), 0, s, partial, (long long)nb, scale, dt_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cfl_blocks(const Geo& pg, const MhdParams& p, const double* reg, const unsigned long long* off,
+                             int nb, int ghost, int bx, int by, int bz, double* partial, double* dt_out,
+                             double scale, hipStream_t s)
+{
+    const long long m = ((long long)bx * by * bz * nb + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_cfl_blocks, dim3((unsigned int)m), dim3(kBlock), 0, s, pg, p, reg, off, nb, ghost, bx, by, bz,
+                       partial);
+    hipLaunchKernelGGL(k_min_final, dim3(1), dim3(kBlock), 0, s, partial, m, scale, dt_out);
     return hipGetLastError();
 }
 

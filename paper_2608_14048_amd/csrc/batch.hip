@@ -195,10 +195,61 @@ __device__ __forceinline__ int dwrap(int i, int n)
     return r < 0 ? r + n : r;
 }
 
-// MODE 0: every block's ghost cells from the blocks that own those domain cells (all 8
-// fields; a face field travels with the cell on its high side).  MODE 1: every padded
-// cell from the domain state dom ([8][NZ][NY][NX]).  MODE 2: the interior cells into
-// dom.  reg: the FP64 register, block b's 8 fields of pc cells at reg + 8 off[b].
+// Every block's ghost cells from the blocks that own those domain cells (all 8 fields;
+// a face field travels with the cell on its high side); one thread per ghost cell: the
+// shell of a padded block is enumerated as its two z slabs (whole planes), then the two
+// y slabs of the interior planes, then the two x slabs of the interior rows.
+__global__ __launch_bounds__(256) void k_ghost_fill(DomainMap m, const unsigned long long* __restrict__ off,
+                                                    int nblocks, double* reg)
+{
+    const int g = m.g, p0 = m.pn[0], p1 = m.pn[1];
+    const long long zs = 2LL * g * p1 * p0, ys = 2LL * g * m.bs[2] * p0, xs = 2LL * g * m.bs[2] * m.bs[1];
+    const long long per = zs + ys + xs;
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= per * nblocks) return;
+    const int b = (int)(t / per);
+    long long q = t - (long long)b * per;
+    int i, j, k;
+    if (q < zs) {
+        const int pz = (int)(q / ((long long)p1 * p0));
+        const long long r = q - (long long)pz * p1 * p0;
+        k = pz < g ? pz : m.bs[2] + pz;
+        j = (int)(r / p0);
+        i = (int)(r - (long long)j * p0);
+    } else if ((q -= zs) < ys) {
+        const int kk = (int)(q / (2LL * g * p0));
+        const long long r = q - (long long)kk * 2 * g * p0;
+        const int jj = (int)(r / p0);
+        k = g + kk;
+        j = jj < g ? jj : m.bs[1] + jj;
+        i = (int)(r - (long long)jj * p0);
+    } else {
+        q -= ys;
+        const int kk = (int)(q / (2LL * g * m.bs[1]));
+        const int r = (int)(q - (long long)kk * 2 * g * m.bs[1]);
+        const int ii = r % (2 * g);
+        k = g + kk;
+        j = g + r / (2 * g);
+        i = ii < g ? ii : m.bs[0] + ii;
+    }
+    const int bi = b % m.nb[0], bj = (b / m.nb[0]) % m.nb[1], bk = b / (m.nb[0] * m.nb[1]);
+    const int I = dwrap(bi * m.bs[0] + i - g, m.dn[0]);
+    const int J = dwrap(bj * m.bs[1] + j - g, m.dn[1]);
+    const int K = dwrap(bk * m.bs[2] + k - g, m.dn[2]);
+    const int oi = I / m.bs[0], oj = J / m.bs[1], ok = K / m.bs[2];
+    const int ob = (ok * m.nb[1] + oj) * m.nb[0] + oi;
+    const long long c = ((long long)k * p1 + j) * p0 + i;
+    const long long oc = ((long long)(K - ok * m.bs[2] + g) * p1 + (J - oj * m.bs[1] + g)) * p0 + (I - oi * m.bs[0] + g);
+    double* blk = reg + off[b] * 8ULL;
+    const double* src = reg + off[ob] * 8ULL;
+#pragma unroll
+    for (int f = 0; f < 8; ++f) blk[f * m.pc + c] = src[f * m.pc + oc];
+}
+
+// MODE 0: every block's ghost cells from their owners (as k_ghost_fill, one thread per
+// padded cell).  MODE 1: every padded cell from the domain state dom ([8][NZ][NY][NX]).
+// MODE 2: the interior cells into dom.  reg: the FP64 register, block b's 8 fields of pc
+// cells at reg + 8 off[b].
 template <int MODE>
 __global__ __launch_bounds__(256) void k_domain_copy(DomainMap m, const unsigned long long* __restrict__ off,
                                                      int nblocks, double* reg, double* dom)
@@ -569,9 +620,12 @@ hipError_t domain_cfl(mhd_batch* c, const char* reg)
 // Conditions"); after the last stage also the domain's CFL step.
 mhd_status domain_after_stage(mhd_batch* c, char* out, bool last)
 {
-    const long long tot = c->dom.pc * c->nb;
-    hipLaunchKernelGGL(k_domain_copy<0>, dim3((unsigned int)((tot + 255) / 256)), dim3(256), 0, c->stream, c->dom,
-                       c->d_off, c->nb, (double*)out, (double*)nullptr);
+    const DomainMap& m = c->dom;
+    const long long per = 2LL * m.g * ((long long)m.pn[1] * m.pn[0] + (long long)m.bs[2] * m.pn[0] +
+                                       (long long)m.bs[2] * m.bs[1]);
+    const long long tot = per * c->nb;
+    hipLaunchKernelGGL(k_ghost_fill, dim3((unsigned int)((tot + 255) / 256)), dim3(256), 0, c->stream, m, c->d_off,
+                       c->nb, (double*)out);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && last) e = domain_cfl(c, out);
     return bdev(e);

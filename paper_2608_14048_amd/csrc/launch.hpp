@@ -88,7 +88,7 @@ hipError_t launch_cfl_mhd(const Geo& g, const MhdParams& p, const double* U, dou
                           double* dt_out, double scale, hipStream_t s);
 // The same over the interior cells of nb equal padded FP64 blocks of grid pg (ghost
 // layers on every side, interior bx x by x bz, block b's register at reg + 8 off[b]
-// doubles); partial: ceil(nb bx by bz / kBlock) doubles.
+// doubles); partial: min(ceil(nb bx by bz / kBlock), 4096) doubles.
 hipError_t launch_cfl_blocks(const Geo& pg, const MhdParams& p, const double* reg, const unsigned long long* off,
                              int nb, int ghost, int bx, int by, int bz, double* partial, double* dt_out,
                              double scale, hipStream_t s);

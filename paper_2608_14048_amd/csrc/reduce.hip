@@ -3,6 +3,8 @@
 // Both are two-pass reductions with a fixed assignment of cells to lanes and of
 // partials to the final pass, so the result is bitwise reproducible run to run.
 // Within a wavefront the 64 lanes combine by butterfly shuffles.
+#include <algorithm>
+
 #include "launch.hpp"
 #include "physics.hpp"
 
@@ -95,14 +97,15 @@ __global__ __launch_bounds__(kBlock) void k_cfl_blocks(Geo pg, MhdParams p, cons
                                                        int bx, int by, int bz, double* __restrict__ partial)
 {
     const long long per = (long long)bx * by * bz;
-    const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
     double r = INFINITY;
-    if (t < per * nb) {
+    // a fixed grid strides over the cells, so the final pass has few partials
+    for (long long t = (long long)blockIdx.x * kBlock + threadIdx.x; t < per * nb;
+         t += (long long)gridDim.x * kBlock) {
         const int b = (int)(t / per);
         const long long q = t - (long long)b * per;
         const int i = (int)(q % bx) + gh, j = (int)((q / bx) % by) + gh, k = (int)(q / ((long long)bx * by)) + gh;
         const long long c = ((long long)k * pg.ny + j) * pg.nx + i;
-        r = cfl_cell(pg, p, reg + off[b] * 8ULL, pg.n, c, c + 1, c + pg.nx, c + (long long)pg.nx * pg.ny);
+        r = min_nan(r, cfl_cell(pg, p, reg + off[b] * 8ULL, pg.n, c, c + 1, c + pg.nx, c + (long long)pg.nx * pg.ny));
     }
     r = block_min(r);
     if (threadIdx.x == 0) partial[blockIdx.x] = r;
@@ -165,7 +168,7 @@ hipError_t launch_cfl_blocks(const Geo& pg, const MhdParams& p, const double* re
                              int nb, int ghost, int bx, int by, int bz, double* partial, double* dt_out,
                              double scale, hipStream_t s)
 {
-    const long long m = ((long long)bx * by * bz * nb + kBlock - 1) / kBlock;
+    const long long m = std::min<long long>(((long long)bx * by * bz * nb + kBlock - 1) / kBlock, 4096);
     hipLaunchKernelGGL(k_cfl_blocks, dim3((unsigned int)m), dim3(kBlock), 0, s, pg, p, reg, off, nb, ghost, bx, by, bz,
                        partial);
     hipLaunchKernelGGL(k_min_final, dim3(1), dim3(kBlock), 0, s, partial, m, scale, dt_out);

@@ -295,7 +295,7 @@ def dust_leg(n: int, steps: int, warmup: int, seed: int = 0, fp32: bool = True):
 PAPER_TABLE = {"A100 (FP64)": 300.0, "MI250X one GCD (FP64)": 250.0}
 
 
-def paper_config_leg(shape, steps: int, warmup: int, precisions=("fp64", "fp32_bulk")):
+def paper_config_leg(shape, steps: int, warmup: int, precisions=("fp64", "fp32_bulk"), blocks: bool = True):
     """The scheme and box of the paper's performance table: oblique linear fast wave,
     RK2 + PLM + HLLE + CT, one block of shape cells; the paper's FP64 numbers on other
     hardware are quoted as context."""
@@ -332,7 +332,7 @@ def paper_config_leg(shape, steps: int, warmup: int, precisions=("fp64", "fp32_b
             out[prec]["l1_reference"] = (f"the FP64 run on the same dt sequence after {len(seq)} steps; "
                                          "relative to the L1 norm of the wave's perturbation")
         del got
-    if "fp64" in out and all(v % 128 == 0 for v in shape):
+    if blocks and "fp64" in out and all(v % 128 == 0 for v in shape):
         out["fp64_128cube_blocks"] = paper_blocks_run(shape, length, state, seq, steps, warmup, ref)
     return out
 
@@ -623,6 +623,8 @@ def main():
     ap.add_argument("--no-paper-config", action="store_true",
                     help="skip the RK2+PLM+HLLE linear-wave leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-meshblock leg")
+    ap.add_argument("--no-paper-blocks", action="store_true",
+                    help="skip the paper box as coupled 128^3 blocks (the one-block runs stay)")
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure leg")
     ap.add_argument("--batch-blocks", type=int, default=512)
     ap.add_argument("--dust-n", type=int, default=192)
@@ -710,7 +712,7 @@ def main():
                                fp32=not args.no_fp32)
     if not args.no_paper_config:
         out["paper_config"] = paper_config_leg(tuple(args.paper_shape), args.side_steps,
-                                               args.side_warmup)
+                                               args.side_warmup, blocks=not args.no_paper_blocks)
     if not args.no_batch:
         out["batch"] = batch_leg(args.batch_blocks, max(args.side_steps // 5, 5), 2, "fp32_bulk", args.seed)
     if not args.no_closure:

@@ -25,10 +25,15 @@ def test_trained_closure_on_a_held_out_seed():
         print(f"  after 4 steps: {last}  ms/step {times}", flush=True)
         for run in ("plain", "closure", "plain_2x"):
             assert all(np.isfinite(v) for v in last[run].values())
-        # the closure must not be worse than the plain coarse step in total energy and
-        # density (held-out mean gains at 8 steps: about 29 % and 11 %)
-        assert last["closure"]["E"] <= last["plain"]["E"]
-        assert last["closure"]["rho"] <= 1.02 * last["plain"]["rho"]
+        # the closure must cut the plain coarse step's error in every class: on this
+        # seed after 4 steps the measured ratios closure / plain are rho 0.889, M 0.909,
+        # E 0.682, B 0.944 (seeds 904-906 after 8 steps: 0.886-0.896, 0.910-0.918,
+        # 0.713-0.722, 0.949-0.953); the bounds leave about 4 points for rounding-level
+        # changes, not for a closure that stops working
+        bounds = {"rho": 0.93, "M": 0.95, "E": 0.78, "B": 0.98}
+        for k, bnd in bounds.items():
+            ratio = last["closure"][k] / last["plain"][k]
+            assert ratio <= bnd, (k, ratio, bnd)
         # conservation and div B of a closure step
         f = LC.FineToCoarse(905, nc, r)
         st = f.filtered()

@@ -21,6 +21,10 @@
 // Each block advances by its own time step (the blocks are separate problems): the
 // step reads dt[b] from device memory, either written from the caller's host array or
 // left there by the CFL reduction of the previous step.
+//
+// Coupled blocks (mhd_batch_couple): equal blocks become one periodic domain, each
+// block a slab of it padded by ghost layers; after every stage one kernel refills every
+// ghost cell from the block that owns it, and every block takes the domain's one step.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -34,6 +34,7 @@ def _pair(shape, block, scheme, seed, ghost=None):
     ((32, 32, 32), (16, 16, 16), VL2_PPM_HLLD, 6),   # 2 x 2 x 2 blocks, PPM: 4 ghost layers
     ((48, 16, 16), (16, 16, 16), VL2_PPM_HLLD, 3),   # a row of 3 blocks (neighbours on both sides differ)
     ((16, 16, 16), (16, 16, 16), VL2_PPM_HLLD, 3),   # one block: its ghosts are its own periodic images
+    ((30, 20, 12), (10, 10, 6), RK2_PLM_HLLE, 4),    # 3 x 2 x 2 blocks of odd sizes (ragged tiles everywhere)
 ])
 def test_blocks_match_one_grid_bitwise(shape, block, scheme, steps):
     st, sim, dom = _pair(shape, block, scheme, seed=7)

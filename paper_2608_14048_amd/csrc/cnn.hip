@@ -121,11 +121,15 @@ __global__ __launch_bounds__(kThreads) void k_cnn_input(Geo g, double gamma, con
     const double ke = 0.5 * rho * ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
     const double p = (gamma - 1.0) * ((U[4 * n + c] - ke) - 0.5 * ((b[0] * b[0] + b[1] * b[1]) + b[2] * b[2]));
     const double w[8] = {rho, v[0], v[1], v[2], p, b[0], b[1], b[2]};
-    bf16_t* o = X0 + (size_t)c * 16;
+    // the voxel's 16 channels (8 used, 8 zero padding) as two 16-byte stores
+    uint32_t h[4];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) o[q] = f2bf((float)((w[q] - mu[q]) / sd[q]));
-#pragma unroll
-    for (int q = 8; q < 16; ++q) o[q] = 0;
+    for (int q = 0; q < 4; ++q)
+        h[q] = (uint32_t)f2bf((float)((w[2 * q] - mu[2 * q]) / sd[2 * q])) |
+               (uint32_t)f2bf((float)((w[2 * q + 1] - mu[2 * q + 1]) / sd[2 * q + 1])) << 16;
+    uint4* o = reinterpret_cast<uint4*>(X0 + (size_t)c * 16);
+    o[0] = uint4{h[0], h[1], h[2], h[3]};
+    o[1] = uint4{0u, 0u, 0u, 0u};
 }
 
 // Y[v][nn] = sum_t sum_k X[v + off(t)][k] B[t][nn][k] (+ bias), 32 outputs.
